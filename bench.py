@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the speculative progressive raycasting hot path on one MI355X.
+
+Workload (default): a 512^3 float32 turbulence-like field (64 seeded Fourier
+modes with |k|^-5/3 amplitude, seed 2), compressed at 4 bits/value in 4^3
+blocks (64 MiB), rendered at 1280x720 at the field's 60th-percentile
+isovalue from a 10-position seeded orbit, with the decoded-block cache capped
+at 512*10^6 bytes.
+
+One step = one render request from start to finish: rebuild the macrocell
+grids from the resident compressed stream (load-time step), compute the
+initial rays, then run passes (speculative traversal, mark, cache update and
+decode, pair build, block raytrace, composite, compaction) until every ray has
+terminated.  Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "rays/s & ms/pass at 1280x720, batched vs plain, same accuracy; blocks decoded/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# Algorithmic bytes per kernel of a pass, in this library's data layout: every
+# input and output byte the kernel must move once (cached re-reads not
+# counted).  Counts are summed over the timed passes:
+#   A rays, S pair slots (N_act*N_spec), P pairs, Ps served pairs, V visible
+#   blocks, K active blocks, M decoded blocks, R bits/value.
+def kernel_bytes(name, c, rate):
+    A, S, P, Ps = c["rays"], c["pair_slots"], c["pairs"], c["served_pairs"]
+    V, K, M = c["visible_blocks"], c["active_blocks"], c["blocks_decoded"]
+    model = {
+        "k_traverse": 8 * A + 4 * S + 32 * V,
+        "k_mark": 4 * S + 16 * P + 8 * V + 16 * K,
+        "k_lookup": 8 * V + 24 * K + 8 * M,
+        "k_assign": 32 * M,
+        "k_decode_scatter": (8 * rate + 268) * M + 4 * S + 28 * Ps,
+        "k_raytrace": 36 * Ps + 532 * V,
+        "k_composite": 8 * A + 4 * S + 20 * P,
+        "k_compact": 12 * A,
+    }
+    return model.get(name)
+
+
+def make_inputs(args):
+    import volgen
+    n = args.n
+    t0 = time.perf_counter()
+    field = volgen.fourier(n, n, n, seed=2, nmode=64, kmax=24, period=float(n))
+    iso = volgen.percentile_value(field, 0.6)
+    stream = volgen.encode(field, args.rate)
+    log(f"[bench] inputs: {n}^3 fourier, rate {args.rate}, iso {iso:.6g}, {stream.nbytes / 2**20:.1f} MiB "
+        f"({time.perf_counter() - t0:.1f}s)")
+    cams = [volgen.orbit_camera(n, n, n, seed=2, k=k, npos=10) for k in range(10)]
+    return field, stream, iso, cams
+
+
+def cpu_baseline(args, stream, iso, cams):
+    """The oracle as it stands, timed on this host on the whole orbit of the
+    workload (10 views at full resolution) after one whole-volume decode."""
+    import numpy as np
+    import oracle
+    n = args.n
+    t0 = time.perf_counter()
+    dec = oracle.decode_volume(stream, (n, n, n), args.rate)
+    t_dec = time.perf_counter() - t0
+    views = cams[: args.cpu_views]
+    entered = hits = 0
+    t0 = time.perf_counter()
+    for cam in views:
+        r = oracle.render(dec, cam, iso, args.w, args.h)
+        entered += int(r["entered"].sum())
+        hits += int(np.isfinite(r["t"]).sum())
+    t_r = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    nblk = ((n + 3) // 4) ** 3
+    return {"value": round(entered / t_r, 1), "unit": "rays/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(views)} orbit views at {args.w}x{args.h} ({entered} rays entered), after one "
+                      f"whole-volume decode timed separately",
+            "render_s": round(t_r, 3), "decode_s": round(t_dec, 3), "decode_blocks_per_s": round(nblk / t_dec, 1),
+            "hits": hits}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--rate", type=int, default=4)
+    ap.add_argument("--w", type=int, default=1280)
+    ap.add_argument("--h", type=int, default=720)
+    ap.add_argument("--spec-cap", type=int, default=16)
+    ap.add_argument("--cache-bytes", type=int, default=512 * 10**6)
+    ap.add_argument("--sweep", default="1,2,4,8,16", help="speculation caps for the sweep ('' = none)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-views", type=int, default=10)
+    ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus N > 1 is not supported",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2309_10212_amd import spr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    field, stream, iso, cams = make_inputs(args)
+    n = args.n
+    ctx = spr.Context(device=0, cache_bytes=args.cache_bytes, spec_cap=args.spec_cap)
+    vol = ctx.load_volume(stream, (n, n, n), args.rate)
+    torch.cuda.synchronize()
+
+    def step(k, cap):
+        vol.build_grids()
+        r = spr.Render(vol, cams[k % len(cams)], iso, args.w, args.h, spec_cap=cap)
+        r.run()
+        info = r.info()
+        r.free()
+        return info
+
+    # load-time step on its own (decode every block once for its range)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        vol.build_grids()
+    torch.cuda.synchronize()
+    load_ms = (time.perf_counter() - t0) * 1e3 / 3
+
+    for i in range(args.warmup):
+        step(i, args.spec_cap)
+    torch.cuda.synchronize()
+
+    ctx.profile(not args.no_profile, reset=True)
+    c0 = ctx.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        infos.append(step(args.warmup + i, args.spec_cap))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile(False)
+    c1 = ctx.counters()
+    ktimes = ctx.kernel_times()
+    dc = {k: c1[k] - c0[k] for k in c1}
+    elapsed = t1 - t0
+    rays = sum(i["rays_entered"] for i in infos)
+    passes = sum(i["passes"] for i in infos)
+    value = rays / elapsed
+    dev_ms = sum(ms for ms, _ in ktimes.values())
+    dec_ms = ktimes.get("k_decode_scatter", (0.0, 0))[0]
+
+    # roofline of the dominant kernel (largest device time in the timed region)
+    dom = max(ktimes.items(), key=lambda kv: kv[1][0])
+    dname, (dms, dn) = dom
+    byts = kernel_bytes(dname, dc, args.rate)
+    roof = None
+    if byts is not None and dn > 0 and dms > 0:
+        per_launch = byts / dn
+        avg_s = dms / dn / 1e3
+        ach = per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 6), "traffic": None, "kernel": dname,
+                "bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_s * 1e6, 2)}
+
+    # speculation sweep over the whole orbit (outside the timed region)
+    sweep = []
+    if args.sweep:
+        for cap in [int(x) for x in args.sweep.split(",") if x]:
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            inf = [step(k, cap) for k in range(len(cams))]
+            torch.cuda.synchronize()
+            s1 = time.perf_counter()
+            rr = sum(i["rays_entered"] for i in inf)
+            pp = sum(i["passes"] for i in inf)
+            sweep.append({"spec_cap": cap, "rays_per_s": round(rr / (s1 - s0)), "passes_per_view": pp / len(inf),
+                          "ms_per_pass": round((s1 - s0) * 1e3 / pp, 4), "ms_per_view": round((s1 - s0) * 1e3 / len(inf), 3),
+                          "utilization": round(sum(i["pairs"] for i in inf) / (pp * args.w * args.h), 4)})
+            log(f"[bench] sweep cap {cap}: {sweep[-1]}")
+
+    cur, peak = ctx.mem_stats()
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args, stream, iso, cams)
+        log(f"[bench] cpu baseline: {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"fourier{n}_rate{args.rate}_{args.w}x{args.h}_cap{args.spec_cap}",
+                   "volume": f"{n}^3 float32, 64 Fourier modes |k|^-5/3 (seed 2), {args.rate} bits/value",
+                   "image": f"{args.w}x{args.h}", "isovalue": "60th percentile of the field",
+                   "spec_cap": args.spec_cap, "cache_bytes": args.cache_bytes,
+                   "step": "grid rebuild + initial rays + passes to completion, one orbit view"},
+        "ms_per_pass": round(elapsed * 1e3 / max(passes, 1), 4),
+        "device_ms_per_pass": round(dev_ms / max(passes, 1), 4),
+        "passes_per_step": passes / args.steps,
+        "blocks_decoded_per_s": round(dc["blocks_decoded"] / elapsed, 1),
+        "blocks_decoded_per_decode_s": round(dc["blocks_decoded"] / (dec_ms / 1e3), 1) if dec_ms > 0 else None,
+        "load_ms": round(load_ms, 4),
+        "peak_mem_bytes": peak,
+        "counters": dc,
+        "kernels_ms_per_launch": {k: round(ms / max(nl, 1), 5) for k, (ms, nl) in ktimes.items()},
+        "roofline": roof,
+        "sweep": sweep,
+        "cpu_baseline": cpu,
+    }
+    vol.free()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,255 @@
+/*
+ * spr.h — C ABI of libspr: speculative progressive isosurface raycasting of a
+ * block-compressed volume on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Usher, Dyken, Kumar, "Speculative Progressive Raycasting for Memory
+ * Constrained Isosurface Visualization of Massive Volumes" (arXiv 2309.10212).
+ * The calls follow the paper's problem statement: a compressed volume is
+ * uploaded once (Sec. 3 overview); every new camera or isovalue computes new
+ * rays (Sec. 3.2); passes repeat until every ray has terminated, and the
+ * partial image is available after each pass (Sec. 3, pipeline figure (a)-(f)).
+ *
+ * Conventions
+ *  - Every call returns an spr_status; 0 is success.  No C++ exception
+ *    crosses this boundary.  On failure spr_last_error() returns a
+ *    thread-local message.  NULL handles and out-pointers are rejected with
+ *    SPR_E_INVALID.
+ *  - Ownership: the library copies host inputs (volume_load) and writes into
+ *    caller buffers (read_*).  Device memory belongs to the handles and comes
+ *    from the context's allocator (hipMalloc when none is given).  Destroy
+ *    renders and batches first, then volumes, then the context.
+ *  - Streams: a context issues all work on one HIP stream (spr_config.stream,
+ *    0 = the null stream).  Calls are stream-ordered and return without
+ *    waiting, except those documented as synchronising: render_done,
+ *    render_run, batch_pass, batch_run, read_*, debug_*, mem_stats, and any
+ *    call given a non-NULL spr_pass_stats.
+ *  - Threading: a context and everything created from it must be used from
+ *    one thread at a time.
+ */
+#ifndef SPR_H
+#define SPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t spr_status;
+#define SPR_OK 0
+#define SPR_E_INVALID (-1)       /* bad argument, handle or descriptor */
+#define SPR_E_OOM (-2)           /* device or host allocation failed */
+#define SPR_E_HIP (-3)           /* a HIP runtime call failed */
+#define SPR_E_CORRUPT (-4)       /* compressed stream inconsistent with its descriptor */
+#define SPR_E_CAPACITY (-5)      /* decoded-block cache cannot hold one block and its neighbours */
+#define SPR_E_STATE (-6)         /* call not valid in the handle's current state */
+#define SPR_E_UNIMPLEMENTED (-7)
+
+#define SPR_NONE 0xFFFFFFFFu     /* "no block" sentinel (Sec. 3.3 uses UINT_MAX) */
+#define SPR_CODEC_VERSION 1u
+#define SPR_DTYPE_F32 0u
+#define SPR_DTYPE_U8 1u
+
+typedef struct spr_ctx spr_ctx;
+typedef struct spr_volume spr_volume;
+typedef struct spr_render spr_render;
+typedef struct spr_batch spr_batch;
+
+/* Device allocator hooks.  alloc returns a device pointer (NULL on failure);
+ * free releases it.  Python passes torch's caching allocator here. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, size_t bytes, void *user);
+    void *user;
+} spr_allocator;
+
+typedef struct {
+    int device;            /* HIP device ordinal */
+    void *stream;          /* hipStream_t; NULL = null stream */
+    size_t cache_bytes;    /* decoded-block cache capacity; 256 B per slot (Sec. 3.5) */
+    uint32_t spec_cap;     /* default speculation cap for new renders (Sec. 4: 64); 0 -> 64 */
+    uint32_t flags;        /* reserved, must be 0 */
+    spr_allocator alloc;   /* optional; alloc.alloc == NULL -> hipMalloc/hipFree */
+} spr_config;
+
+/* A compressed volume (Sec. 3 overview: fixed-rate block compression).
+ * nx, ny, nz >= 2 samples; rate_bits in 1..16 (coded) or 32 (raw float32);
+ * src_dtype records what the samples were before conversion to float32;
+ * codec_version must be SPR_CODEC_VERSION.  The stream holds
+ * ceil(nx/4)*ceil(ny/4)*ceil(nz/4) records of 8*rate_bits bytes, block
+ * (bx,by,bz) at index bx + nbx*(by + nby*bz). */
+typedef struct {
+    uint32_t nx, ny, nz;
+    uint32_t rate_bits;
+    uint32_t src_dtype;
+    uint32_t codec_version;
+} spr_volume_desc;
+
+/* Pinhole camera (Sec. 3.2): eye, look-at point, up vector, vertical field
+ * of view in degrees.  Coordinates are in sample units: sample (i,j,k) sits
+ * at the point (i,j,k). */
+typedef struct {
+    double eye[3], center[3], up[3];
+    double vfov_deg;
+} spr_camera;
+
+/* Per-pixel hit record: ray parameter t (unit-length direction, sample
+ * units), block id of the hit cell, cell index (cx&3)+4(cy&3)+16(cz&3).
+ * No hit: t = +inf, block_id = cell = SPR_NONE. */
+typedef struct {
+    double t;
+    uint32_t block_id;
+    uint32_t cell;
+} spr_hit;
+
+/* Counters of one pass (Sec. 5 statistics: speculation count, utilization as
+ * ray-block pairs over w*h slots, blocks visible per pass, memory). */
+typedef struct {
+    uint32_t pass;            /* 1-based pass index of this render */
+    uint32_t n_active;        /* active rays at the start of the pass */
+    uint32_t n_spec;          /* speculation count used by the pass */
+    uint32_t pairs;           /* ray-block pairs written (R_BID entries != NONE) */
+    uint32_t visible_blocks;  /* distinct blocks in the pairs */
+    uint32_t active_blocks;   /* visible blocks plus their +x/+y/+z neighbours */
+    uint32_t blocks_decoded;  /* cache misses decompressed this pass */
+    uint32_t deferred_pairs;  /* pairs postponed because the cache was too small */
+    uint32_t terminated;      /* rays that terminated this pass */
+    uint32_t reserved;
+    double utilization;       /* pairs / (w*h) */
+    float ms;                 /* device time of the pass (HIP events) */
+    float pad;
+} spr_pass_stats;
+
+/* Cumulative device counters of a context since its creation. */
+typedef struct {
+    uint64_t passes;          /* passes run (single renders and batches) */
+    uint64_t blocks_decoded;  /* cache misses decompressed */
+    uint64_t visible_blocks;  /* sum over passes of visible blocks */
+    uint64_t active_blocks;   /* sum over passes of active blocks */
+    uint64_t pairs;           /* sum over passes of ray-block pairs */
+    uint64_t evicted;         /* cache slots reclaimed by LRU sweeps */
+    uint64_t overflow;        /* passes whose slot supply fell short (0 by construction) */
+    uint64_t rays;            /* sum over passes of active rays */
+    uint64_t pair_slots;      /* sum over passes of N_act * N_spec (R_BID entries written) */
+    uint64_t served_pairs;    /* sum over passes of pairs raytraced */
+} spr_counters;
+
+/* Per-render summary. */
+typedef struct {
+    uint32_t w, h;
+    uint32_t rays_entered;    /* rays that entered the volume (Sec. 3.2) */
+    uint32_t n_active;        /* rays still active */
+    uint32_t n_spec;          /* speculation count of the next pass */
+    uint32_t passes;          /* passes run */
+    uint64_t pairs;           /* ray-block pairs over all passes */
+} spr_render_info;
+
+/* Accumulated device time of one kernel of the pass (profiling mode). */
+typedef struct {
+    const char *name;         /* static string owned by the library */
+    double total_ms;
+    uint64_t launches;
+} spr_kernel_time;
+
+/* ---------------------------------------------------------------- context */
+spr_status spr_ctx_create(const spr_config *cfg, spr_ctx **out);
+spr_status spr_ctx_destroy(spr_ctx *ctx);
+/* Device bytes currently held by the context and its objects, and the peak. */
+spr_status spr_mem_stats(spr_ctx *ctx, size_t *current, size_t *peak);
+/* Cumulative counters (synchronises). */
+spr_status spr_ctx_counters(spr_ctx *ctx, spr_counters *out);
+/* Profiling mode: when enabled, passes run eagerly (not from a captured
+ * graph) with a HIP event recorded on the context stream before and after
+ * every kernel; per-kernel device times accumulate until reset. */
+spr_status spr_ctx_profile(spr_ctx *ctx, int enable, int reset);
+/* Copy up to max per-kernel totals (synchronises); *n = kernels reported. */
+spr_status spr_ctx_kernel_times(spr_ctx *ctx, spr_kernel_time *out, uint32_t max, uint32_t *n);
+
+/* ----------------------------------------------------------------- volume */
+/* Upload a compressed volume and build its macrocell grids (Sec. 3.1): every
+ * block is decoded once to get its value range; the fine grid (one cell per
+ * block) unions each block's range with its +x/+y/+z neighbours' (the 2x2x2
+ * block neighbourhood), and the coarse grid (one cell per 4^3 blocks) unions
+ * the fine ranges inside it.  host_stream is read before the call returns.
+ * Errors: SPR_E_INVALID (bad descriptor), SPR_E_CORRUPT (bytes != expected
+ * stream size), SPR_E_OOM. */
+spr_status spr_volume_load(spr_ctx *ctx, const void *host_stream, size_t bytes, const spr_volume_desc *desc,
+                           spr_volume **out);
+spr_status spr_volume_free(spr_volume *vol);
+/* Recompute the macrocell grids of a resident volume from its device stream
+ * (the same load-time step as spr_volume_load, without the host upload).
+ * Enqueued; must not overlap a pass that reads the grids. */
+spr_status spr_volume_build_grids(spr_volume *vol);
+/* Debug/parity: copy the fine (per block) and coarse (per 4^3 blocks) value
+ * ranges, as interleaved (lo, hi) float pairs, into host buffers of
+ * fine_count / coarse_count pairs (NULL to skip).  Synchronises. */
+spr_status spr_volume_ranges(spr_volume *vol, float *fine_lohi, size_t fine_count, float *coarse_lohi,
+                             size_t coarse_count);
+/* Debug/parity: decode n listed blocks with the device decoder into
+ * host_out[i*64 .. i*64+63] (raster order x + 4y + 16z).  Synchronises. */
+spr_status spr_debug_decode_blocks(spr_volume *vol, const uint32_t *ids, uint32_t n, float *host_out);
+
+/* Debug/parity: sqrt(x[i]) and x[i] / y[i] in fp64 on the device, compiled
+ * exactly like the hit test (which relies on IEEE correctly rounded fp64
+ * division and square root); n values, host arrays.  Synchronises. */
+spr_status spr_debug_fp64_ops(spr_ctx *ctx, const double *x, const double *y, size_t n, double *sqrt_out,
+                              double *div_out);
+
+/* ----------------------------------------------------------------- render */
+/* Start a render: computes every pixel's ray and its entry into the volume
+ * (Sec. 3.2); rays that miss are terminated, the image is cleared to 0 and
+ * the hit buffer to "no hit".  w*h must be < 2^24; the camera must not look
+ * along its up vector.  isovalue is compared in float32. */
+spr_status spr_render_begin(spr_volume *vol, const spr_camera *cam, float isovalue, uint32_t w, uint32_t h,
+                            spr_render **out);
+/* Speculation cap of this render (Sec. 4 caps N_spec at 64); 1 disables
+ * speculation.  Only before the first pass.  SPR_E_STATE afterwards. */
+spr_status spr_render_set_spec_cap(spr_render *r, uint32_t cap);
+/* Enqueue one pass (Sec. 3 (a)-(f), Sec. 4): speculative traversal, mark
+ * visible/active blocks, LRU cache update and decompression of misses, build
+ * the per-block ray lists, raytrace visible blocks, depth composite, count
+ * and compact the active rays and update N_spec.  A pass on a finished
+ * render does nothing.  With opt_stats != NULL the call synchronises and
+ * fills the counters. */
+spr_status spr_render_pass(spr_render *r, spr_pass_stats *opt_stats);
+/* Synchronise and report whether every ray has terminated (N_act == 0). */
+spr_status spr_render_done(spr_render *r, int *done);
+/* Run passes until done or max_passes; *passes_run = passes executed.
+ * Synchronises. */
+spr_status spr_render_run(spr_render *r, uint32_t max_passes, uint32_t *passes_run);
+/* Summary of a render (synchronises). */
+spr_status spr_render_get_info(spr_render *r, spr_render_info *out);
+/* Copy the RGBA8 image (w*h*4 bytes, row 0 at the top, r in the low byte)
+ * or the hit buffer (w*h records) to host memory.  Synchronises. */
+spr_status spr_read_image(spr_render *r, uint8_t *rgba, size_t bytes);
+spr_status spr_read_hits(spr_render *r, spr_hit *hits, size_t count);
+/* Device pointers of the image (uint32 RGBA per pixel) and hit buffer; valid
+ * until the render is freed; contents change with each pass. */
+spr_status spr_render_device_ptrs(spr_render *r, void **rgba, void **hits);
+spr_status spr_render_free(spr_render *r);
+
+/* ------------------------------------------------------------------ batch */
+/* A batch advances many renders (any volumes and image sizes of one
+ * context) by one pass per call, with one launch sequence for all of them;
+ * the launch sequence of a pass is captured once into a HIP graph and
+ * replayed.  The renders stay owned by the caller and must outlive the batch;
+ * each may belong to at most one live batch. */
+spr_status spr_batch_create(spr_ctx *ctx, uint32_t n, spr_render *const *renders, spr_batch **out);
+/* One pass of every unfinished render; synchronises and reports how many
+ * renders are still unfinished. */
+spr_status spr_batch_pass(spr_batch *b, uint32_t *n_unfinished);
+/* Passes until every render is done or max_passes; polls completion every
+ * poll_every passes (0 -> 1).  Synchronises. */
+spr_status spr_batch_run(spr_batch *b, uint32_t max_passes, uint32_t poll_every, uint32_t *passes_run);
+spr_status spr_batch_free(spr_batch *b);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *spr_last_error(void);
+/* Library version string. */
+const char *spr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPR_H */

@@ -51,7 +51,7 @@ def _load():
         lib.orc_decode_volume.argtypes = [P, ctypes.c_size_t, i, i, i, i, P]
         lib.orc_grids.argtypes = [P, i, i, i, P, P, P]
         lib.orc_render.argtypes = [P, i, i, i, ctypes.POINTER(_Cam), ctypes.c_float, i, i, P,
-                                   ctypes.c_size_t, P, P, P, P]
+                                   ctypes.c_size_t, P, P, P, P, P]
         lib.orc_cell_walk.argtypes = [i, i, i, ctypes.POINTER(_Cam), i, i, i, i, P, P, ctypes.c_long, P]
         lib.orc_cell_walk.restype = ctypes.c_long
         lib.orc_ray.argtypes = [i, i, i, ctypes.POINTER(_Cam), i, i, i, i, P]
@@ -141,7 +141,8 @@ def grids(vol: np.ndarray):
 def render(vol: np.ndarray, cam, iso: float, w: int, h: int, pixels=None):
     """First-hit isosurface per pixel by marching every dual cell (Sec. 3.3-3.7).
 
-    Returns dict of arrays t (f64, inf = no hit), block, cell, rgba (u32)."""
+    Returns dict of arrays t (f64, inf = no hit), block, cell, rgba (u32) and
+    entered (bool: the ray entered the volume)."""
     nx, ny, nz = _dims(vol)
     v = np.ascontiguousarray(vol, np.float32)
     if pixels is None:
@@ -154,11 +155,12 @@ def render(vol: np.ndarray, cam, iso: float, w: int, h: int, pixels=None):
     b = np.empty(n, np.uint32)
     c = np.empty(n, np.uint32)
     rgba = np.empty(n, np.uint32)
+    ent = np.empty(n, np.uint8)
     cc = _cam(cam)
     _ok(_load().orc_render(_p(v), nx, ny, nz, ctypes.byref(cc), ctypes.c_float(iso), w, h,
-                           _p(pix) if pix is not None else None, n, _p(t), _p(b), _p(c), _p(rgba)),
+                           _p(pix) if pix is not None else None, n, _p(t), _p(b), _p(c), _p(rgba), _p(ent)),
         "render")
-    return {"t": t, "block": b, "cell": c, "rgba": rgba}
+    return {"t": t, "block": b, "cell": c, "rgba": rgba, "entered": ent.astype(bool)}
 
 
 def cell_walk(dims, cam, w: int, h: int, px: int, py: int, cap: int = 1 << 16):

@@ -288,6 +288,7 @@ static void make_ray(const cam_basis *b, int nx, int ny, int nz, int px, int py,
     for (int a = 0; a < 3; ++a) {
         ray->o[a] = b->eye[a];
         ray->d[a] = v[a] * inv;
+        if (fabs(ray->d[a]) < 1e-290) ray->d[a] = 0.0;   /* treated as parallel to the axis */
         ray->r[a] = ray->d[a] != 0.0 ? 1.0 / ray->d[a] : 0.0;
     }
     /* slab test against the sample domain [0, n-1]^3 */
@@ -550,7 +551,7 @@ static void trace_pixel(const float *vol, int nx, int ny, int nz, const cam_basi
  * otherwise pix[i] is a raster pixel index.  Outputs are per listed pixel. */
 int orc_render(const float *vol, int nx, int ny, int nz, const orc_camera *cam, float iso, int w, int h,
                const uint32_t *pix, size_t npix, double *t_out, uint32_t *block_out, uint32_t *cell_out,
-               uint32_t *rgba_out) {
+               uint32_t *rgba_out, uint8_t *entered_out) {
     if (!vol || !cam || w < 1 || h < 1 || nx < 2 || ny < 2 || nz < 2) return ORC_EINVAL;
     cam_basis cb;
     if (make_basis(cam, w, h, &cb)) return ORC_EINVAL;
@@ -567,6 +568,7 @@ int orc_render(const float *vol, int nx, int ny, int nz, const orc_camera *cam, 
         if (block_out) block_out[i] = r.block;
         if (cell_out) cell_out[i] = r.cell;
         if (rgba_out) rgba_out[i] = r.rgba;
+        if (entered_out) entered_out[i] = (uint8_t)r.entered;
     }
     return ORC_OK;
 }

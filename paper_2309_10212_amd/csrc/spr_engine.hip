@@ -1,0 +1,959 @@
+// spr_engine.hip — host engine and C ABI of libspr (see include/spr.h).
+//
+// Owns the handles, device memory, the shared decoded-block cache, the pass
+// workspace and the launch tables; sequences the load path, the initial-ray
+// pass and the per-pass kernels on the context's stream; captures the pass
+// of a batch into a HIP graph and replays it.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "spr_launch.h"
+
+using namespace spr;
+
+namespace {
+
+thread_local std::string g_err;
+
+spr_status fail(spr_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+spr_status fail(spr_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(SPR_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define CHK(expr)                        \
+    do {                                 \
+        spr_status s_ = (expr);          \
+        if (s_ != SPR_OK) return s_;     \
+    } while (0)
+
+uint32_t round64h(uint64_t x) { return (uint32_t)((x + 63u) & ~63ull); }
+
+}  // namespace
+
+struct spr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    spr_allocator alloc{};
+    uint32_t spec_cap = 64;
+    size_t mem_cur = 0, mem_peak = 0;
+    PassCtl *ctl = nullptr;
+    VolDev *d_vols = nullptr;
+    VolDev h_vols[MAX_VOLUMES];
+    spr_volume *vol_handles[MAX_VOLUMES] = {};
+    Cache cache{};
+    Work work{};
+    uint64_t work_gen = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
+    bool prof = false;
+    hipEvent_t prof_ev[PASS_KERNELS + 1] = {};
+    double prof_ms[PASS_KERNELS] = {};
+    uint64_t prof_n[PASS_KERNELS] = {};
+    void *pinned = nullptr;     // small host staging area
+    int n_renders = 0;
+};
+
+struct spr_volume {
+    spr_ctx *ctx = nullptr;
+    uint32_t idx = 0;
+    spr_volume_desc desc{};
+    size_t stream_bytes = 0;
+    int n_renders = 0;
+};
+
+struct spr_render {
+    spr_ctx *ctx = nullptr;
+    spr_volume *vol = nullptr;
+    uint32_t w = 0, h = 0, npix = 0;
+    ReqDev hreq{};
+    ReqDev *d_req = nullptr;
+    ReqState *d_st = nullptr;
+    Table table{};
+    PassGrids grids{};
+    bool started = false;       // a pass has run
+    spr_batch *batch = nullptr;
+    float last_ms = 0.f;
+};
+
+struct spr_batch {
+    spr_ctx *ctx = nullptr;
+    std::vector<spr_render *> renders;
+    Table table{};
+    PassGrids grids{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t graph_gen = ~0ull;
+};
+
+namespace {
+
+// ------------------------------------------------------------- memory ------
+
+spr_status dev_alloc(spr_ctx *c, size_t bytes, void **out) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (c->alloc.alloc) {
+        p = c->alloc.alloc(bytes, c->alloc.user);
+        if (!p) return fail(SPR_E_OOM, "allocator callback failed for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SPR_E_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        }
+    }
+    c->mem_cur += bytes;
+    if (c->mem_cur > c->mem_peak) c->mem_peak = c->mem_cur;
+    *out = p;
+    return SPR_OK;
+}
+
+void dev_free(spr_ctx *c, void *p, size_t bytes) {
+    if (!p) return;
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (c->alloc.alloc) {
+        if (c->alloc.free) c->alloc.free(p, bytes, c->alloc.user);
+    } else {
+        (void)hipFree(p);
+    }
+    c->mem_cur -= bytes;
+}
+
+template <typename T>
+spr_status dalloc(spr_ctx *c, size_t count, T **out) {
+    void *p;
+    CHK(dev_alloc(c, count * sizeof(T), &p));
+    *out = (T *)p;
+    return SPR_OK;
+}
+
+template <typename T>
+void dfree(spr_ctx *c, T *&p, size_t count) {
+    dev_free(c, (void *)p, count * sizeof(T));
+    p = nullptr;
+}
+
+// --------------------------------------------------------- camera basis ----
+// Pinhole basis in fp64 (the per-pixel part runs on the device):
+// fwd = normalize(center - eye); right = normalize(fwd x up); up' = right x fwd;
+// sy = tan(vfov/2), sx = sy * (w/h).  normalize(v) = v * (1 / sqrt((x^2+y^2)+z^2)).
+bool make_basis(const spr_camera *c, uint32_t w, uint32_t h, ReqDev &q) {
+    double f[3] = {c->center[0] - c->eye[0], c->center[1] - c->eye[1], c->center[2] - c->eye[2]};
+    double fl = sqrt((f[0] * f[0] + f[1] * f[1]) + f[2] * f[2]);
+    if (!(fl > 0)) return false;
+    double inv = 1.0 / fl;
+    for (int a = 0; a < 3; ++a) q.fwd[a] = f[a] * inv;
+    double r[3] = {q.fwd[1] * c->up[2] - q.fwd[2] * c->up[1], q.fwd[2] * c->up[0] - q.fwd[0] * c->up[2],
+                   q.fwd[0] * c->up[1] - q.fwd[1] * c->up[0]};
+    double rl = sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+    if (!(rl > 0)) return false;
+    inv = 1.0 / rl;
+    for (int a = 0; a < 3; ++a) q.right[a] = r[a] * inv;
+    q.upv[0] = q.right[1] * q.fwd[2] - q.right[2] * q.fwd[1];
+    q.upv[1] = q.right[2] * q.fwd[0] - q.right[0] * q.fwd[2];
+    q.upv[2] = q.right[0] * q.fwd[1] - q.right[1] * q.fwd[0];
+    double th = tan((c->vfov_deg * 0.5) * (3.14159265358979323846 / 180.0));
+    q.sx = th * ((double)w / (double)h);
+    q.sy = th;
+    for (int a = 0; a < 3; ++a) q.eye[a] = c->eye[a];
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(q.eye[a]) || !isfinite(q.fwd[a]) || !isfinite(q.right[a])) return false;
+    return isfinite(th) && th > 0;
+}
+
+PassGrids grids_for(const spr_ctx *c, uint64_t max_A, uint64_t max_P) {
+    auto g = [](uint64_t n, uint64_t per, uint32_t cap) {
+        uint64_t x = (n + per - 1) / per;
+        if (x < 1) x = 1;
+        if (x > cap) x = cap;
+        return (uint32_t)x;
+    };
+    PassGrids pg;
+    pg.rays = g(max_A, 256, 2048);
+    pg.pairs = g(max_P, 256, 2048);
+    pg.blocks = g(8 * max_P, 256, 2048);
+    pg.slots = g(c->cache.n_slots, 256, 2048);
+    pg.decode = 2048;
+    pg.scatter = g(max_P, 64, 4096);
+    return pg;
+}
+
+spr_status ensure_work(spr_ctx *c, uint64_t P) {
+    if (P <= c->work.cap_P) return SPR_OK;
+    if (P > 0xFFFFFFFFull / 8) return fail(SPR_E_INVALID, "pair space of %llu too large", (unsigned long long)P);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    Work &W = c->work;
+    size_t oP = W.cap_P, oK = W.cap_K;
+    dfree(c, W.vis_list, oP); dfree(c, W.vis_cnt, oP); dfree(c, W.vis_off, oP);
+    dfree(c, W.act_list, oK); dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
+    dfree(c, W.pair_rank, oP); dfree(c, W.s_ray, oP); dfree(c, W.s_q, oP); dfree(c, W.s_vi, oP);
+    W.cap_P = 0; W.cap_K = 0;
+    uint64_t cP = P, cK = 8 * P;
+    CHK(dalloc(c, cP, &W.vis_list)); CHK(dalloc(c, cP, &W.vis_cnt)); CHK(dalloc(c, cP, &W.vis_off));
+    CHK(dalloc(c, cK, &W.act_list)); CHK(dalloc(c, cK, &W.miss_list)); CHK(dalloc(c, cK, &W.miss_slot));
+    CHK(dalloc(c, cP, &W.pair_rank)); CHK(dalloc(c, cP, &W.s_ray)); CHK(dalloc(c, cP, &W.s_q));
+    CHK(dalloc(c, cP, &W.s_vi));
+    W.cap_P = (uint32_t)cP;
+    W.cap_K = (uint32_t)cK;
+    c->work_gen++;
+    return SPR_OK;
+}
+
+spr_status alloc_table(spr_ctx *c, uint32_t nreq, uint64_t max_A, uint64_t max_P, Table &T) {
+    T.nreq = nreq;
+    T.max_A = (uint32_t)max_A;
+    T.max_P = (uint32_t)max_P;
+    CHK(dalloc(c, nreq + 1, &T.act_base));
+    CHK(dalloc(c, nreq + 1, &T.pair_base));
+    CHK(dalloc(c, max_A / 64 + 2, &T.wave_cnt));
+    CHK(dalloc(c, max_A / 64 + 2, &T.wave_off));
+    return SPR_OK;
+}
+
+void free_table(spr_ctx *c, Table &T) {
+    dfree(c, T.act_base, T.nreq + 1);
+    dfree(c, T.pair_base, T.nreq + 1);
+    dfree(c, T.wave_cnt, T.max_A / 64 + 2);
+    dfree(c, T.wave_off, T.max_A / 64 + 2);
+}
+
+spr_status read_state(spr_ctx *c, const ReqState *d, ReqState *h) {
+    HIPCHK(hipMemcpyAsync(c->pinned, d, sizeof(ReqState), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    memcpy(h, c->pinned, sizeof(ReqState));
+    return SPR_OK;
+}
+
+spr_status read_ctl(spr_ctx *c, PassCtl *h) {
+    HIPCHK(hipMemcpyAsync((char *)c->pinned + 256, c->ctl, sizeof(PassCtl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    memcpy(h, (char *)c->pinned + 256, sizeof(PassCtl));
+    return SPR_OK;
+}
+
+// One pass of a launch table, eager; in profiling mode with per-kernel events.
+spr_status run_pass(spr_ctx *c, const Table &T, const PassGrids &g) {
+    if (!c->prof) {
+        HIPCHK(launch_pass(c->stream, c->ctl, T, c->d_vols, c->work, c->cache, g, nullptr));
+        return SPR_OK;
+    }
+    HIPCHK(launch_pass(c->stream, c->ctl, T, c->d_vols, c->work, c->cache, g, c->prof_ev));
+    HIPCHK(hipEventSynchronize(c->prof_ev[PASS_KERNELS]));
+    for (int k = 0; k < PASS_KERNELS; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->prof_ev[k], c->prof_ev[k + 1]));
+        c->prof_ms[k] += ms;
+        c->prof_n[k] += 1;
+    }
+    return SPR_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ====
+
+extern "C" {
+
+const char *spr_last_error(void) { return g_err.c_str(); }
+
+const char *spr_version(void) { return "spr 0.1 (gfx950, codec 1)"; }
+
+spr_status spr_ctx_create(const spr_config *cfg, spr_ctx **out) {
+    if (!cfg || !out) return fail(SPR_E_INVALID, "null argument");
+    *out = nullptr;
+    if (cfg->flags != 0) return fail(SPR_E_INVALID, "flags must be 0");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (cfg->device < 0 || cfg->device >= ndev) return fail(SPR_E_INVALID, "device %d out of range", cfg->device);
+    uint64_t slots = cfg->cache_bytes / 256;
+    if (slots < 8) return fail(SPR_E_CAPACITY, "cache of %zu bytes holds fewer than 8 blocks", cfg->cache_bytes);
+    if (slots > 0x7FFFFFFFull) return fail(SPR_E_INVALID, "cache too large");
+    HIPCHK(hipSetDevice(cfg->device));
+    spr_ctx *c = new (std::nothrow) spr_ctx();
+    if (!c) return fail(SPR_E_OOM, "host allocation failed");
+    c->device = cfg->device;
+    c->stream = (hipStream_t)cfg->stream;
+    c->alloc = cfg->alloc;
+    c->spec_cap = cfg->spec_cap ? cfg->spec_cap : 64;
+    spr_status st;
+#define CTX_TRY(expr)           \
+    do {                        \
+        st = (expr);            \
+        if (st != SPR_OK) {     \
+            spr_ctx_destroy(c); \
+            return st;          \
+        }                       \
+    } while (0)
+    CTX_TRY(dalloc(c, 1, &c->ctl));
+    CTX_TRY(dalloc(c, MAX_VOLUMES, &c->d_vols));
+    c->cache.n_slots = (uint32_t)slots;
+    CTX_TRY(dalloc(c, slots * 64, &c->cache.slots));
+    CTX_TRY(dalloc(c, slots, &c->cache.owner));
+    CTX_TRY(dalloc(c, slots, &c->cache.stamp));
+    CTX_TRY(dalloc(c, slots, &c->cache.free_stack));
+    if (hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+        spr_ctx_destroy(c);
+        return fail(SPR_E_OOM, "pinned host allocation failed");
+    }
+    bool evok = true;
+    for (auto &e : c->prof_ev) evok = evok && hipEventCreate(&e) == hipSuccess;
+    if (!evok || hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        spr_ctx_destroy(c);
+        return fail(SPR_E_HIP, "hipEventCreate failed");
+    }
+    PassCtl h{};
+    h.n_slots = (uint32_t)slots;
+    h.free_top = (uint32_t)slots;
+    h.evict_T = 64;
+    memcpy(c->pinned, &h, sizeof(h));
+    if (hipMemcpyAsync(c->ctl, c->pinned, sizeof(h), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        launch_fill_u64(c->stream, c->cache.owner, slots, ~0ull) != hipSuccess ||
+        launch_fill_u32(c->stream, c->cache.stamp, slots, 0) != hipSuccess ||
+        launch_iota_u32(c->stream, c->cache.free_stack, slots) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        spr_ctx_destroy(c);
+        return fail(SPR_E_HIP, "context initialisation failed");
+    }
+#undef CTX_TRY
+    *out = c;
+    return SPR_OK;
+}
+
+spr_status spr_ctx_destroy(spr_ctx *c) {
+    if (!c) return fail(SPR_E_INVALID, "null context");
+    (void)hipSetDevice(c->device);
+    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    Work &W = c->work;
+    size_t oP = W.cap_P, oK = W.cap_K;
+    dfree(c, W.vis_list, oP); dfree(c, W.vis_cnt, oP); dfree(c, W.vis_off, oP);
+    dfree(c, W.act_list, oK); dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
+    dfree(c, W.pair_rank, oP); dfree(c, W.s_ray, oP); dfree(c, W.s_q, oP); dfree(c, W.s_vi, oP);
+    size_t ns = c->cache.n_slots;
+    dfree(c, c->cache.slots, ns * 64);
+    dfree(c, c->cache.owner, ns);
+    dfree(c, c->cache.stamp, ns);
+    dfree(c, c->cache.free_stack, ns);
+    dfree(c, c->ctl, 1);
+    dfree(c, c->d_vols, MAX_VOLUMES);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (auto &e : c->prof_ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+    return SPR_OK;
+}
+
+spr_status spr_mem_stats(spr_ctx *c, size_t *current, size_t *peak) {
+    if (!c) return fail(SPR_E_INVALID, "null context");
+    if (current) *current = c->mem_cur;
+    if (peak) *peak = c->mem_peak;
+    return SPR_OK;
+}
+
+spr_status spr_ctx_counters(spr_ctx *c, spr_counters *o) {
+    if (!c || !o) return fail(SPR_E_INVALID, "null argument");
+    HIPCHK(hipSetDevice(c->device));
+    PassCtl p;
+    CHK(read_ctl(c, &p));
+    memset(o, 0, sizeof(*o));
+    o->passes = p.acc_passes;
+    o->blocks_decoded = p.acc_decoded;
+    o->visible_blocks = p.acc_visible;
+    o->active_blocks = p.acc_active;
+    o->pairs = p.acc_pairs;
+    o->evicted = p.acc_evicted;
+    o->overflow = p.acc_overflow;
+    o->rays = p.acc_rays;
+    o->pair_slots = p.acc_slots;
+    o->served_pairs = p.acc_served;
+    return SPR_OK;
+}
+
+spr_status spr_ctx_profile(spr_ctx *c, int enable, int reset) {
+    if (!c) return fail(SPR_E_INVALID, "null context");
+    c->prof = enable != 0;
+    if (reset) {
+        for (int k = 0; k < PASS_KERNELS; ++k) { c->prof_ms[k] = 0; c->prof_n[k] = 0; }
+    }
+    return SPR_OK;
+}
+
+spr_status spr_ctx_kernel_times(spr_ctx *c, spr_kernel_time *out, uint32_t max, uint32_t *n) {
+    if (!c || !n || (!out && max)) return fail(SPR_E_INVALID, "null argument");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    uint32_t k = 0;
+    for (; k < (uint32_t)PASS_KERNELS && k < max; ++k) {
+        out[k].name = PASS_KERNEL_NAMES[k];
+        out[k].total_ms = c->prof_ms[k];
+        out[k].launches = c->prof_n[k];
+    }
+    *n = k;
+    return SPR_OK;
+}
+
+// ----------------------------------------------------------------- volume --
+
+static void free_volume_buffers(spr_ctx *c, VolDev &V, size_t stream_bytes) {
+    uint64_t nb = V.nblocks;
+    uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    dev_free(c, (void *)V.stream, stream_bytes);
+    V.stream = nullptr;
+    dfree(c, V.fine, nb);
+    dfree(c, V.coarse, nc);
+    dfree(c, V.map, nb);
+    dfree(c, V.vis_stamp, nb);
+    dfree(c, V.vis_idx, nb);
+    dfree(c, V.act_stamp, nb);
+    dfree(c, V.blk, nb);
+}
+
+spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, const spr_volume_desc *d,
+                           spr_volume **out) {
+    if (!c || !host_stream || !d || !out) return fail(SPR_E_INVALID, "null argument");
+    *out = nullptr;
+    if (d->codec_version != SPR_CODEC_VERSION) return fail(SPR_E_INVALID, "unknown codec version %u", d->codec_version);
+    if (d->nx < 2 || d->ny < 2 || d->nz < 2) return fail(SPR_E_INVALID, "volume must have at least 2 samples per axis");
+    if (!((d->rate_bits >= 1 && d->rate_bits <= 16) || d->rate_bits == 32))
+        return fail(SPR_E_INVALID, "rate_bits %u not in 1..16 or 32", d->rate_bits);
+    if (d->src_dtype != SPR_DTYPE_F32 && d->src_dtype != SPR_DTYPE_U8) return fail(SPR_E_INVALID, "bad src_dtype");
+    uint64_t nbx = (d->nx + 3) / 4, nby = (d->ny + 3) / 4, nbz = (d->nz + 3) / 4;
+    uint64_t nb = nbx * nby * nbz;
+    if (nb >= 0xFFFFFFF0ull) return fail(SPR_E_INVALID, "too many blocks");
+    uint64_t expect = nb * 8ull * d->rate_bits;
+    if (bytes != expect)
+        return fail(SPR_E_CORRUPT, "stream has %zu bytes, descriptor needs %llu", bytes, (unsigned long long)expect);
+    int idx = -1;
+    for (int i = 0; i < MAX_VOLUMES; ++i)
+        if (!c->vol_handles[i]) { idx = i; break; }
+    if (idx < 0) return fail(SPR_E_CAPACITY, "too many volumes in one context");
+    HIPCHK(hipSetDevice(c->device));
+    VolDev V{};
+    V.n[0] = (int)d->nx; V.n[1] = (int)d->ny; V.n[2] = (int)d->nz;
+    for (int a = 0; a < 3; ++a) {
+        V.nb[a] = (V.n[a] + 3) / 4;
+        V.nc[a] = (V.nb[a] + 3) / 4;
+        V.tb[a] = (V.n[a] - 1 + 3) / 4;
+        V.tc[a] = (V.tb[a] + 3) / 4;
+    }
+    V.rate = (int)d->rate_bits;
+    V.rec_words = 2 * (int)d->rate_bits;
+    V.nblocks = nb;
+    V.live = 1;
+    uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    spr_status st = SPR_OK;
+    void *sp = nullptr;
+    do {
+        if ((st = dev_alloc(c, bytes, &sp)) != SPR_OK) break;
+        V.stream = (const uint32_t *)sp;
+        if ((st = dalloc(c, nb, &V.fine)) != SPR_OK) break;
+        if ((st = dalloc(c, nc, &V.coarse)) != SPR_OK) break;
+        if ((st = dalloc(c, nb, &V.map)) != SPR_OK) break;
+        if ((st = dalloc(c, nb, &V.vis_stamp)) != SPR_OK) break;
+        if ((st = dalloc(c, nb, &V.vis_idx)) != SPR_OK) break;
+        if ((st = dalloc(c, nb, &V.act_stamp)) != SPR_OK) break;
+        if ((st = dalloc(c, nb, &V.blk)) != SPR_OK) break;
+    } while (0);
+    if (st != SPR_OK) {
+        free_volume_buffers(c, V, bytes);
+        return st;
+    }
+    hipError_t e = hipMemcpyAsync(sp, host_stream, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.map, nb, NONE);
+    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.vis_stamp, nb, 0);
+    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.vis_idx, nb, 0);
+    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.act_stamp, nb, 0);
+    if (e == hipSuccess) e = launch_load_grids(c->stream, V);
+    c->h_vols[idx] = V;
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_vols + idx, &c->h_vols[idx], sizeof(VolDev), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        free_volume_buffers(c, V, bytes);
+        return fail(SPR_E_HIP, "volume upload failed: %s", hipGetErrorString(e));
+    }
+    spr_volume *v = new (std::nothrow) spr_volume();
+    if (!v) {
+        free_volume_buffers(c, V, bytes);
+        return fail(SPR_E_OOM, "host allocation failed");
+    }
+    v->ctx = c;
+    v->idx = (uint32_t)idx;
+    v->desc = *d;
+    v->stream_bytes = bytes;
+    c->vol_handles[idx] = v;
+    *out = v;
+    return SPR_OK;
+}
+
+spr_status spr_volume_free(spr_volume *v) {
+    if (!v) return fail(SPR_E_INVALID, "null volume");
+    spr_ctx *c = v->ctx;
+    if (v->n_renders) return fail(SPR_E_STATE, "volume still has %d live renders", v->n_renders);
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(launch_release_volume(c->stream, c->ctl, c->cache, v->idx));
+    VolDev &V = c->h_vols[v->idx];
+    V.live = 0;
+    HIPCHK(hipMemcpyAsync(c->d_vols + v->idx, &V, sizeof(VolDev), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    free_volume_buffers(c, V, v->stream_bytes);
+    c->vol_handles[v->idx] = nullptr;
+    delete v;
+    return SPR_OK;
+}
+
+spr_status spr_volume_build_grids(spr_volume *v) {
+    if (!v) return fail(SPR_E_INVALID, "null volume");
+    spr_ctx *c = v->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(launch_load_grids(c->stream, c->h_vols[v->idx]));
+    return SPR_OK;
+}
+
+spr_status spr_volume_ranges(spr_volume *v, float *fine, size_t fine_count, float *coarse, size_t coarse_count) {
+    if (!v) return fail(SPR_E_INVALID, "null volume");
+    spr_ctx *c = v->ctx;
+    const VolDev &V = c->h_vols[v->idx];
+    uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    if (fine && fine_count != V.nblocks) return fail(SPR_E_INVALID, "fine_count must be %llu", (unsigned long long)V.nblocks);
+    if (coarse && coarse_count != nc) return fail(SPR_E_INVALID, "coarse_count must be %llu", (unsigned long long)nc);
+    HIPCHK(hipSetDevice(c->device));
+    if (fine) HIPCHK(hipMemcpyAsync(fine, V.fine, V.nblocks * sizeof(float2), hipMemcpyDeviceToHost, c->stream));
+    if (coarse) HIPCHK(hipMemcpyAsync(coarse, V.coarse, nc * sizeof(float2), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SPR_OK;
+}
+
+spr_status spr_debug_decode_blocks(spr_volume *v, const uint32_t *ids, uint32_t n, float *host_out) {
+    if (!v || (!ids && n) || (!host_out && n)) return fail(SPR_E_INVALID, "null argument");
+    if (n == 0) return SPR_OK;
+    spr_ctx *c = v->ctx;
+    const VolDev &V = c->h_vols[v->idx];
+    for (uint32_t i = 0; i < n; ++i)
+        if (ids[i] >= V.nblocks) return fail(SPR_E_INVALID, "block id %u out of range", ids[i]);
+    HIPCHK(hipSetDevice(c->device));
+    uint32_t *d_ids = nullptr;
+    float *d_out = nullptr;
+    CHK(dalloc(c, n, &d_ids));
+    spr_status st = dalloc(c, (size_t)n * 64, &d_out);
+    if (st != SPR_OK) {
+        dfree(c, d_ids, n);
+        return st;
+    }
+    hipError_t e = hipMemcpyAsync(d_ids, ids, n * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_decode_ids(c->stream, V, d_ids, n, d_out);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_out, d_out, (size_t)n * 64 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(c, d_ids, n);
+    dfree(c, d_out, (size_t)n * 64);
+    if (e != hipSuccess) return fail(SPR_E_HIP, "debug decode failed: %s", hipGetErrorString(e));
+    return SPR_OK;
+}
+
+spr_status spr_debug_fp64_ops(spr_ctx *c, const double *x, const double *y, size_t n, double *sq, double *dv) {
+    if (!c || ((!x || !y || !sq || !dv) && n)) return fail(SPR_E_INVALID, "null argument");
+    if (n == 0) return SPR_OK;
+    HIPCHK(hipSetDevice(c->device));
+    double *buf = nullptr;
+    CHK(dalloc(c, 4 * n, &buf));
+    hipError_t e = hipMemcpyAsync(buf, x, n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(buf + n, y, n * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_fp64_ops(c->stream, buf, buf + n, n, buf + 2 * n, buf + 3 * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(sq, buf + 2 * n, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dv, buf + 3 * n, n * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(c, buf, 4 * n);
+    if (e != hipSuccess) return fail(SPR_E_HIP, "fp64 probe failed: %s", hipGetErrorString(e));
+    return SPR_OK;
+}
+
+// ----------------------------------------------------------------- render --
+
+static void free_render_buffers(spr_ctx *c, spr_render *r) {
+    uint32_t n = r->npix;
+    ReqDev &q = r->hreq;
+    dfree(c, q.ray_state, n);
+    dfree(c, q.act[0], n);
+    dfree(c, q.act[1], n);
+    dfree(c, q.pair_blk, n);
+    dfree(c, q.rgbz, n);
+    dfree(c, q.image, n);
+    dfree(c, q.hits, n);
+    dfree(c, r->d_st, 1);
+    dfree(c, r->d_req, 1);
+    free_table(c, r->table);
+}
+
+spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uint32_t w, uint32_t h,
+                            spr_render **out) {
+    if (!v || !cam || !out) return fail(SPR_E_INVALID, "null argument");
+    *out = nullptr;
+    if (w == 0 || h == 0) return fail(SPR_E_INVALID, "empty image");
+    uint64_t npix = (uint64_t)w * h;
+    if (npix >= (1ull << 24)) return fail(SPR_E_INVALID, "w*h must be < 2^24");
+    if (!isfinite(iso)) return fail(SPR_E_INVALID, "isovalue must be finite");
+    spr_ctx *c = v->ctx;
+    spr_render *r = new (std::nothrow) spr_render();
+    if (!r) return fail(SPR_E_OOM, "host allocation failed");
+    r->ctx = c;
+    r->vol = v;
+    r->w = w; r->h = h; r->npix = (uint32_t)npix;
+    ReqDev &q = r->hreq;
+    if (!make_basis(cam, w, h, q)) {
+        delete r;
+        return fail(SPR_E_INVALID, "degenerate camera (zero view direction or view along up)");
+    }
+    q.iso = iso;
+    q.w = w; q.h = h; q.npix = (uint32_t)npix;
+    q.vol = v->idx;
+    q.spec_cap = c->spec_cap;
+    HIPCHK(hipSetDevice(c->device));
+    spr_status st = SPR_OK;
+    do {
+        if ((st = dalloc(c, npix, &q.ray_state)) != SPR_OK) break;
+        if ((st = dalloc(c, npix, &q.act[0])) != SPR_OK) break;
+        if ((st = dalloc(c, npix, &q.act[1])) != SPR_OK) break;
+        if ((st = dalloc(c, npix, &q.pair_blk)) != SPR_OK) break;
+        if ((st = dalloc(c, npix, &q.rgbz)) != SPR_OK) break;
+        if ((st = dalloc(c, npix, &q.image)) != SPR_OK) break;
+        if ((st = dalloc(c, npix, &q.hits)) != SPR_OK) break;
+        if ((st = dalloc(c, 1, &r->d_st)) != SPR_OK) break;
+        if ((st = dalloc(c, 1, &r->d_req)) != SPR_OK) break;
+        if ((st = alloc_table(c, 1, round64h(npix), npix, r->table)) != SPR_OK) break;
+        st = ensure_work(c, npix);
+    } while (0);
+    if (st != SPR_OK) {
+        free_render_buffers(c, r);
+        delete r;
+        return st;
+    }
+    q.st = r->d_st;
+    r->table.reqs = r->d_req;
+    r->grids = grids_for(c, round64h(npix), npix);
+    ReqState s0{};
+    s0.n_act = (uint32_t)npix;
+    s0.cur = 1;
+    hipError_t e = hipMemcpy(r->d_st, &s0, sizeof(s0), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->d_req, &q, sizeof(q), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols);
+    if (e != hipSuccess) {
+        free_render_buffers(c, r);
+        delete r;
+        return fail(SPR_E_HIP, "render set-up failed: %s", hipGetErrorString(e));
+    }
+    v->n_renders++;
+    c->n_renders++;
+    *out = r;
+    return SPR_OK;
+}
+
+spr_status spr_render_set_spec_cap(spr_render *r, uint32_t cap) {
+    if (!r) return fail(SPR_E_INVALID, "null render");
+    if (cap < 1 || cap > 4096) return fail(SPR_E_INVALID, "spec cap must be in 1..4096");
+    if (r->started) return fail(SPR_E_STATE, "speculation cap can only change before the first pass");
+    if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
+    spr_ctx *c = r->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    ReqState s;
+    CHK(read_state(c, r->d_st, &s));
+    r->hreq.spec_cap = cap;
+    if (s.n_act > 0) {
+        uint32_t ns = r->npix / s.n_act;
+        if (ns < 1) ns = 1;
+        if (ns > cap) ns = cap;
+        s.n_spec = ns;
+    }
+    HIPCHK(hipMemcpy(r->d_st, &s, sizeof(s), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(r->d_req, &r->hreq, sizeof(ReqDev), hipMemcpyHostToDevice));
+    return SPR_OK;
+}
+
+static spr_status fill_stats(spr_render *r, spr_pass_stats *o, float ms) {
+    spr_ctx *c = r->ctx;
+    ReqState s;
+    PassCtl p;
+    CHK(read_state(c, r->d_st, &s));
+    CHK(read_ctl(c, &p));
+    memset(o, 0, sizeof(*o));
+    o->pass = s.passes;
+    o->n_active = s.n_act_prev;
+    o->n_spec = s.last_nspec;
+    o->pairs = s.last_pairs;
+    o->visible_blocks = p.n_vis;
+    o->active_blocks = p.n_actblk;
+    o->blocks_decoded = p.n_miss;
+    o->deferred_pairs = s.last_deferred;
+    o->terminated = s.last_terminated;
+    o->utilization = r->npix ? (double)s.last_pairs / (double)r->npix : 0.0;
+    o->ms = ms;
+    return SPR_OK;
+}
+
+spr_status spr_render_pass(spr_render *r, spr_pass_stats *stats) {
+    if (!r) return fail(SPR_E_INVALID, "null render");
+    if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
+    spr_ctx *c = r->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    if (stats) HIPCHK(hipEventRecord(c->ev0, c->stream));
+    CHK(run_pass(c, r->table, r->grids));
+    r->started = true;
+    if (stats) {
+        HIPCHK(hipEventRecord(c->ev1, c->stream));
+        HIPCHK(hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        CHK(fill_stats(r, stats, ms));
+    }
+    return SPR_OK;
+}
+
+spr_status spr_render_done(spr_render *r, int *done) {
+    if (!r || !done) return fail(SPR_E_INVALID, "null argument");
+    spr_ctx *c = r->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    ReqState s;
+    CHK(read_state(c, r->d_st, &s));
+    *done = s.n_act == 0;
+    return SPR_OK;
+}
+
+spr_status spr_render_run(spr_render *r, uint32_t max_passes, uint32_t *passes_run) {
+    if (!r) return fail(SPR_E_INVALID, "null render");
+    if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
+    uint32_t n = 0;
+    int done = 0;
+    CHK(spr_render_done(r, &done));
+    while (!done && n < max_passes) {
+        CHK(spr_render_pass(r, nullptr));
+        ++n;
+        CHK(spr_render_done(r, &done));
+    }
+    if (passes_run) *passes_run = n;
+    return SPR_OK;
+}
+
+spr_status spr_render_get_info(spr_render *r, spr_render_info *o) {
+    if (!r || !o) return fail(SPR_E_INVALID, "null argument");
+    spr_ctx *c = r->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    ReqState s;
+    CHK(read_state(c, r->d_st, &s));
+    memset(o, 0, sizeof(*o));
+    o->w = r->w;
+    o->h = r->h;
+    o->rays_entered = s.passes ? s.entered : s.n_act;
+    o->n_active = s.n_act;
+    o->n_spec = s.n_spec;
+    o->passes = s.passes;
+    o->pairs = s.tot_pairs;
+    return SPR_OK;
+}
+
+spr_status spr_read_image(spr_render *r, uint8_t *rgba, size_t bytes) {
+    if (!r || !rgba) return fail(SPR_E_INVALID, "null argument");
+    if (bytes != (size_t)r->npix * 4) return fail(SPR_E_INVALID, "image needs %zu bytes", (size_t)r->npix * 4);
+    spr_ctx *c = r->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipMemcpyAsync(rgba, r->hreq.image, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SPR_OK;
+}
+
+spr_status spr_read_hits(spr_render *r, spr_hit *hits, size_t count) {
+    if (!r || !hits) return fail(SPR_E_INVALID, "null argument");
+    if (count != r->npix) return fail(SPR_E_INVALID, "hit buffer needs %u records", r->npix);
+    spr_ctx *c = r->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipMemcpyAsync(hits, r->hreq.hits, count * sizeof(spr_hit), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return SPR_OK;
+}
+
+spr_status spr_render_device_ptrs(spr_render *r, void **rgba, void **hits) {
+    if (!r) return fail(SPR_E_INVALID, "null render");
+    if (rgba) *rgba = r->hreq.image;
+    if (hits) *hits = r->hreq.hits;
+    return SPR_OK;
+}
+
+spr_status spr_render_free(spr_render *r) {
+    if (!r) return fail(SPR_E_INVALID, "null render");
+    if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
+    spr_ctx *c = r->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    free_render_buffers(c, r);
+    r->vol->n_renders--;
+    c->n_renders--;
+    delete r;
+    return SPR_OK;
+}
+
+// ------------------------------------------------------------------ batch --
+
+spr_status spr_batch_create(spr_ctx *c, uint32_t n, spr_render *const *renders, spr_batch **out) {
+    if (!c || !out || (n && !renders)) return fail(SPR_E_INVALID, "null argument");
+    *out = nullptr;
+    if (n == 0 || n > MAX_REQS) return fail(SPR_E_INVALID, "batch size must be 1..%d", MAX_REQS);
+    uint64_t A = 0, P = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        spr_render *r = renders[i];
+        if (!r || r->ctx != c) return fail(SPR_E_INVALID, "render %u is null or from another context", i);
+        if (r->batch) return fail(SPR_E_STATE, "render %u already belongs to a batch", i);
+        for (uint32_t j = 0; j < i; ++j)
+            if (renders[j] == r) return fail(SPR_E_INVALID, "render %u listed twice", i);
+        A += round64h(r->npix);
+        P += r->npix;
+    }
+    if (A >= 0xFFFFFFFFull || P > 0xFFFFFFFFull / 8) return fail(SPR_E_INVALID, "batch too large");
+    HIPCHK(hipSetDevice(c->device));
+    spr_batch *b = new (std::nothrow) spr_batch();
+    if (!b) return fail(SPR_E_OOM, "host allocation failed");
+    b->ctx = c;
+    b->renders.assign(renders, renders + n);
+    spr_status st = alloc_table(c, n, A, P, b->table);
+    if (st == SPR_OK) st = dalloc(c, n, &b->table.reqs);
+    if (st == SPR_OK) st = ensure_work(c, P);
+    if (st != SPR_OK) {
+        free_table(c, b->table);
+        dfree(c, b->table.reqs, n);
+        delete b;
+        return st;
+    }
+    std::vector<ReqDev> reqs(n);
+    for (uint32_t i = 0; i < n; ++i) reqs[i] = renders[i]->hreq;
+    hipError_t e = hipMemcpy(b->table.reqs, reqs.data(), n * sizeof(ReqDev), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_table(c, b->table);
+        dfree(c, b->table.reqs, n);
+        delete b;
+        return fail(SPR_E_HIP, "batch set-up failed: %s", hipGetErrorString(e));
+    }
+    b->grids = grids_for(c, A, P);
+    for (auto *r : b->renders) r->batch = b;
+    *out = b;
+    return SPR_OK;
+}
+
+static spr_status batch_launch(spr_batch *b) {
+    spr_ctx *c = b->ctx;
+    if (c->prof) {
+        CHK(run_pass(c, b->table, b->grids));
+        for (auto *r : b->renders) r->started = true;
+        return SPR_OK;
+    }
+    if (b->graph_gen != c->work_gen) {
+        if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+        // record on the private stream (the context stream may be the null
+        // stream, which cannot be captured); replays go to the context stream
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = launch_pass(c->cap_stream, c->ctl, b->table, c->d_vols, c->work, c->cache, b->grids, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(SPR_E_HIP, "pass capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        b->graph = g;
+        HIPCHK(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+        b->graph_gen = c->work_gen;
+    }
+    HIPCHK(hipGraphLaunch(b->exec, c->stream));
+    for (auto *r : b->renders) r->started = true;
+    return SPR_OK;
+}
+
+static spr_status batch_unfinished(spr_batch *b, uint32_t *n_unfinished) {
+    spr_ctx *c = b->ctx;
+    uint32_t n = (uint32_t)b->renders.size();
+    char *dst = (char *)c->pinned + 1024;
+    if (n * sizeof(uint32_t) > 2048) {
+        // large batches: read in chunks through the staging area
+        uint32_t cnt = 0;
+        for (auto *r : b->renders) {
+            ReqState s;
+            CHK(read_state(c, r->d_st, &s));
+            cnt += s.n_act > 0;
+        }
+        *n_unfinished = cnt;
+        return SPR_OK;
+    }
+    for (uint32_t i = 0; i < n; ++i)
+        HIPCHK(hipMemcpyAsync(dst + 4 * i, &b->renders[i]->d_st->n_act, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    uint32_t cnt = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t v;
+        memcpy(&v, dst + 4 * i, 4);
+        cnt += v > 0;
+    }
+    *n_unfinished = cnt;
+    return SPR_OK;
+}
+
+spr_status spr_batch_pass(spr_batch *b, uint32_t *n_unfinished) {
+    if (!b) return fail(SPR_E_INVALID, "null batch");
+    HIPCHK(hipSetDevice(b->ctx->device));
+    CHK(batch_launch(b));
+    uint32_t n = 0;
+    CHK(batch_unfinished(b, &n));
+    if (n_unfinished) *n_unfinished = n;
+    return SPR_OK;
+}
+
+spr_status spr_batch_run(spr_batch *b, uint32_t max_passes, uint32_t poll_every, uint32_t *passes_run) {
+    if (!b) return fail(SPR_E_INVALID, "null batch");
+    if (poll_every == 0) poll_every = 1;
+    HIPCHK(hipSetDevice(b->ctx->device));
+    uint32_t n = 0, left = 0;
+    CHK(batch_unfinished(b, &left));
+    while (left && n < max_passes) {
+        for (uint32_t k = 0; k < poll_every && n < max_passes; ++k) {
+            CHK(batch_launch(b));
+            ++n;
+        }
+        CHK(batch_unfinished(b, &left));
+    }
+    if (passes_run) *passes_run = n;
+    return SPR_OK;
+}
+
+spr_status spr_batch_free(spr_batch *b) {
+    if (!b) return fail(SPR_E_INVALID, "null batch");
+    spr_ctx *c = b->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    free_table(c, b->table);
+    dfree(c, b->table.reqs, b->renders.size());
+    for (auto *r : b->renders) r->batch = nullptr;
+    delete b;
+    return SPR_OK;
+}
+
+}  // extern "C"

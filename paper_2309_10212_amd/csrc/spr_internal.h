@@ -1,0 +1,471 @@
+// spr_internal.h — device-side data layout and inline device routines of
+// libspr (speculative progressive isosurface raycasting, arXiv 2309.10212).
+//
+// Everything here is GPU-path code.  It is compiled with hipcc for gfx950
+// with -ffp-contract=off so that every fp64 expression below evaluates in the
+// written order with IEEE rounding; the hit decision per dual cell depends on
+// that (the canonical forms are documented beside each routine).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/spr.h"
+
+namespace spr {
+
+constexpr uint32_t NONE = 0xFFFFFFFFu;          // no block / empty slot
+constexpr uint32_t RAY_NOT_STARTED = 0xFFFFFFFFu;
+constexpr uint32_t RAY_DONE = 0xFFFFFFFEu;
+constexpr int MAX_VOLUMES = 64;
+constexpr int MAX_REQS = 256;                   // requests per launch table
+constexpr int WAVE = 64;
+
+// ------------------------------------------------------------ device data --
+
+// One loaded volume.  Block ids are local to the volume (bx + nbx*(by + nby*bz)).
+struct VolDev {
+    const uint32_t *stream;     // nblocks records of rec_words 32-bit words
+    float2 *blk;                // per block: own value range (samples inside the volume)
+    float2 *fine;               // per block: union of the 2x2x2 block neighbourhood
+    float2 *coarse;             // per 4^3 blocks: union of fine ranges
+    uint32_t *map;              // per block: cache slot or NONE
+    uint32_t *vis_stamp;        // per block: last pass it was visible
+    uint32_t *vis_idx;          // per block: index in that pass's visible list
+    uint32_t *act_stamp;        // per block: last pass it was active
+    int n[3];                   // samples per axis
+    int nb[3];                  // blocks per axis, ceil(n/4)
+    int nc[3];                  // coarse cells per axis, ceil(nb/4)
+    int tb[3];                  // blocks that own dual cells, ceil((n-1)/4)
+    int tc[3];                  // coarse cells that own dual cells, ceil(tb/4)
+    int rate;                   // bits per value (32 = raw)
+    int rec_words;              // 2*rate
+    uint64_t nblocks;
+    uint32_t live;
+    uint32_t pad;
+};
+
+// Per-pair raytrace result (the RGBZ buffer of Sec. 4.3): t = +inf for no hit.
+struct Rgbz {
+    double t;
+    uint32_t cell;
+    uint32_t rgba;
+};
+
+// Mutable per-render state kept on the device (no host round trip per pass).
+struct ReqState {
+    uint32_t n_act;             // active rays for the next pass
+    uint32_t n_spec;            // speculation count for the next pass
+    uint32_t cur;               // which of the two active-ray lists is current
+    uint32_t passes;            // passes run
+    uint32_t n_act_prev;        // active rays at the start of the last pass
+    uint32_t last_pairs, last_deferred, last_terminated, last_nspec;
+    uint32_t entered;           // rays that entered the volume (set at the first pass)
+    uint32_t pad[2];
+    unsigned long long tot_pairs;
+    uint32_t pad2[2];
+};
+
+// Immutable per-render description (camera basis computed on the host).
+struct ReqDev {
+    double eye[3], fwd[3], right[3], upv[3];
+    double sx, sy;
+    float iso;
+    uint32_t w, h, npix;
+    uint32_t vol;               // index in the context's volume table
+    uint32_t spec_cap;
+    uint32_t *ray_state;        // per pixel: last served block, RAY_NOT_STARTED, RAY_DONE
+    uint32_t *act[2];           // compacted active pixel lists
+    uint32_t *pair_blk;         // per pair slot (R_BID of Sec. 3.3/4.1)
+    Rgbz *rgbz;                 // per pair slot
+    uint32_t *image;            // RGBA8 per pixel
+    spr_hit *hits;              // per pixel
+    ReqState *st;
+};
+
+// Per-pass control block of a context (counters reset at each pass start).
+struct PassCtl {
+    uint32_t pass;              // global pass stamp (starts at 1)
+    uint32_t nreq;
+    uint32_t A;                 // active-ray index space of this pass (64-padded per request)
+    uint32_t P;                 // pair index space of this pass
+    uint32_t n_vis;             // visible blocks appended
+    uint32_t v_adm;             // visible blocks admitted (served) this pass
+    uint32_t n_actblk;          // active blocks appended
+    uint32_t n_miss;            // misses appended
+    uint32_t n_hit;
+    uint32_t cursor;            // sorted-pair allocation cursor
+    uint32_t served;            // served pairs
+    uint32_t deferred;          // pairs on unserved blocks
+    uint32_t n_slots;
+    uint32_t free_top;          // entries in the free-slot stack
+    uint32_t assign_base;       // misses take free_stack[assign_base + i]
+    uint32_t need;              // slots to reclaim by eviction this pass
+    uint32_t evict_T;           // evict occupied slots of age >= evict_T
+    uint32_t evict_done_blocks; // ticket for the histogram's last block
+    uint32_t evicted;
+    uint32_t terminated;
+    uint32_t pairs;
+    uint32_t overflow;          // set if the slot supply ever fell short (never by construction)
+    uint32_t assigned;          // misses that received a slot this pass
+    uint32_t rays;              // active rays of this pass (unpadded)
+    uint32_t pad[8];
+    uint32_t hist[64];
+    // cumulative counters since context creation
+    unsigned long long acc_passes, acc_decoded, acc_visible, acc_active, acc_pairs, acc_evicted, acc_overflow,
+        acc_rays, acc_slots, acc_served;
+};
+
+// Launch table of a pass: the requests advanced together.
+struct Table {
+    ReqDev *reqs;               // nreq entries
+    uint32_t *act_base;         // nreq+1, 64-aligned prefix of n_act
+    uint32_t *pair_base;        // nreq+1, prefix of n_act*n_spec
+    uint32_t *wave_cnt;         // survivors per 64-entry wave of the A space
+    uint32_t *wave_off;
+    uint32_t nreq;
+    uint32_t max_A;             // capacity of the A space (sum of padded npix)
+    uint32_t max_P;             // capacity of the pair space (sum of npix)
+};
+
+// Context-level scratch for one pass, sized for the largest table.
+struct Work {
+    uint64_t *vis_list;         // (vol << 32) | block
+    uint32_t *vis_cnt;          // pairs per visible block
+    uint32_t *vis_off;          // start of the block's run in the sorted pairs
+    uint64_t *act_list;         // active blocks (vol << 32) | block
+    uint64_t *miss_list;        // misses (vol << 32) | block
+    uint32_t *miss_slot;
+    uint32_t *pair_rank;        // per pair index: rank within its block
+    uint32_t *s_ray;            // sorted pairs: (req << 24) | pixel
+    uint32_t *s_q;              // sorted pairs: pair slot within the request
+    uint32_t *s_vi;             // sorted pairs: visible-list index
+    uint32_t cap_P;             // pairs capacity
+    uint32_t cap_K;             // active/miss list capacity
+};
+
+struct Cache {
+    float *slots;               // n_slots * 64 floats
+    uint64_t *owner;            // per slot: (vol << 32) | block, or ~0
+    uint32_t *stamp;            // per slot: last pass used
+    uint32_t *free_stack;
+    uint32_t n_slots;
+};
+
+// ---------------------------------------------------------- wave helpers --
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    uint32_t l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Wave-aggregated append: every active lane calls it; lanes with want get
+// consecutive indices from one atomic on *counter.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool want) {
+    uint64_t m = __ballot(want);
+    if (m == 0) return NONE;
+    uint64_t act = __ballot(1);
+    int leader = __ffsll((unsigned long long)act) - 1;
+    uint32_t base = 0;
+    if ((int)lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+    base = __shfl(base, leader);
+    return want ? base + (uint32_t)__popcll(m & lanemask_lt()) : NONE;
+}
+
+// ------------------------------------------------------------ ray set-up --
+// Camera model (Sec. 3.2 computes per-pixel rays; the pinhole form is this
+// library's reading): for pixel (px, py), row 0 at the top,
+//   x = ((2(px + 1/2))/w - 1) * sx,   y = (1 - (2(py + 1/2))/h) * sy,
+//   v = (fwd + x right) + y up,       d = v * (1 / sqrt((vx^2 + vy^2) + vz^2)),
+// all in fp64 in exactly this order; components below 1e-290 in magnitude are
+// set to 0 (the ray is parallel to that axis); r_a = 1/d_a.  t_enter/t_exit come from
+// the slab test against the sample domain [0, n-1]^3 with the same plane
+// parameter function tau_a(m) = (m - o_a) * r_a used by every walk level.
+
+struct Ray {
+    double o[3], d[3], r[3];
+    double te, tx;
+    int entered;
+};
+
+__device__ __forceinline__ double tau_at(const Ray &R, int a, int m) { return ((double)m - R.o[a]) * R.r[a]; }
+
+__device__ inline void make_ray(const ReqDev &q, const int n[3], uint32_t pix, Ray &R) {
+    int px = (int)(pix % q.w), py = (int)(pix / q.w);
+    double ndx = (2.0 * ((double)px + 0.5)) / (double)q.w - 1.0;
+    double ndy = 1.0 - (2.0 * ((double)py + 0.5)) / (double)q.h;
+    double x = ndx * q.sx, y = ndy * q.sy;
+    double v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = (q.fwd[a] + x * q.right[a]) + y * q.upv[a];
+    double inv = 1.0 / sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        R.o[a] = q.eye[a];
+        R.d[a] = v[a] * inv;
+        if (fabs(R.d[a]) < 1e-290) R.d[a] = 0.0;   // keeps every 1/d_a finite
+        R.r[a] = R.d[a] != 0.0 ? 1.0 / R.d[a] : 0.0;
+    }
+    double te = 0.0, tx = __builtin_inf();
+    int ent = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double np, fp;
+        if (R.d[a] > 0.0) { np = tau_at(R, a, 0); fp = tau_at(R, a, n[a] - 1); }
+        else if (R.d[a] < 0.0) { np = tau_at(R, a, n[a] - 1); fp = tau_at(R, a, 0); }
+        else {
+            if (R.o[a] < 0.0 || R.o[a] > (double)(n[a] - 1)) ent = 0;
+            continue;
+        }
+        if (np > te) te = np;
+        if (fp < tx) tx = fp;
+    }
+    if (te > tx) ent = 0;
+    R.te = te;
+    R.tx = tx;
+    R.entered = ent;
+}
+
+// ------------------------------------------------- multi-level cell walk --
+// A level has cells of S samples per axis (S = 1 dual cells, 4 blocks, 16
+// coarse cells) and L[a] cells per axis.  Its plane m sits at S*m, except the
+// top plane m = L[a], which is the domain face n-1 (so leaving the domain is
+// seen identically at every level).  The cell holding the ray at parameter t
+// is, for d > 0, the largest m whose lower plane has tau <= t; for d < 0 the
+// smallest m whose upper plane has tau <= t; for d == 0 the cell of the
+// origin.  Stepping crosses every plane with tau <= the nearest exit-plane
+// parameter, so tied planes are crossed together and all levels see one
+// consistent sequence.
+
+struct Level {
+    int S;
+    int L[3];
+    int n[3];
+};
+
+__device__ __forceinline__ int plane_pos(const Level &lv, int a, int m) {
+    return m >= lv.L[a] ? lv.n[a] - 1 : lv.S * m;
+}
+
+__device__ __forceinline__ double tau_plane(const Ray &R, const Level &lv, int a, int m) {
+    return tau_at(R, a, plane_pos(lv, a, m));
+}
+
+// origin cell on a d == 0 axis, at level S
+__device__ __forceinline__ int still_cell(const Ray &R, const Level &lv, int a) {
+    double f = floor(R.o[a]);
+    int m;
+    if (f < 0.0) m = 0;
+    else if (f > (double)(lv.n[a] - 2)) m = lv.n[a] - 2;
+    else m = (int)f;
+    return m / lv.S;
+}
+
+// cell index on axis a at parameter t, searched in [lo, hi] starting from a guess
+__device__ inline int cell_at(const Ray &R, const Level &lv, int a, double t, int lo, int hi) {
+    if (R.d[a] == 0.0) return still_cell(R, lv, a);
+    double p = R.o[a] + t * R.d[a];
+    int g = (int)floor(p / (double)lv.S);
+    if (g < lo) g = lo;
+    if (g > hi) g = hi;
+    if (R.d[a] > 0.0) {
+        while (g < hi && tau_plane(R, lv, a, g + 1) <= t) ++g;
+        while (g > lo && tau_plane(R, lv, a, g) > t) --g;
+    } else {
+        while (g > lo && tau_plane(R, lv, a, g) <= t) --g;
+        while (g < hi && tau_plane(R, lv, a, g + 1) > t) ++g;
+    }
+    return g;
+}
+
+// parameter where the ray leaves cell c (min over axes of the exit planes)
+__device__ __forceinline__ double cell_exit(const Ray &R, const Level &lv, const int c[3]) {
+    double tn = __builtin_inf();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (R.d[a] > 0.0) { double x = tau_plane(R, lv, a, c[a] + 1); if (x < tn) tn = x; }
+        else if (R.d[a] < 0.0) { double x = tau_plane(R, lv, a, c[a]); if (x < tn) tn = x; }
+    }
+    return tn;
+}
+
+// parameter where the ray enters cell c (max of t_enter and the entry planes)
+__device__ __forceinline__ double cell_entry(const Ray &R, const Level &lv, const int c[3]) {
+    double t0 = R.te;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (R.d[a] > 0.0) { double e = tau_plane(R, lv, a, c[a]); if (e > t0) t0 = e; }
+        else if (R.d[a] < 0.0) { double e = tau_plane(R, lv, a, c[a] + 1); if (e > t0) t0 = e; }
+    }
+    return t0;
+}
+
+// Cross every plane with tau <= tn.  Returns false when the ray leaves
+// [lo, hi] on some axis (for the full range: leaves the domain).
+__device__ inline bool advance(const Ray &R, const Level &lv, int c[3], double tn, const int lo[3], const int hi[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (R.d[a] > 0.0) {
+            while (tau_plane(R, lv, a, c[a] + 1) <= tn) {
+                ++c[a];
+                if (c[a] > hi[a]) return false;
+            }
+        } else if (R.d[a] < 0.0) {
+            while (tau_plane(R, lv, a, c[a]) <= tn) {
+                --c[a];
+                if (c[a] < lo[a]) return false;
+            }
+        }
+    }
+    return true;
+}
+
+// ------------------------------------------------------------ cell test --
+// Canonical hit test of dual cell (i,j,k) over [t0, t1] (Sec. 3.7, after
+// Marmitt et al.): corners c_{abg} (a fastest) as fp64; local entry point
+// (u0,v0,w0) = (o + t0 d) - (i,j,k); each axis factor is linear in
+// s in [0, S]: X0 = (1-u0) - s dx, X1 = u0 + s dx; the cubic
+// g(s) = A s^3 + B s^2 + C s + D is accumulated corner by corner in index
+// order with the products grouped as written below; D -= iso.  Extrema are
+// the roots of 3A s^2 + 2B s + C in (0, S); the first exact zero or strict
+// sign change over {0, extrema, S} decides the hit.  The root inside the
+// bracket is refined by safeguarded Newton-bisection.
+
+struct CellHit {
+    int hit;
+    double s;
+    double loc[3];
+};
+
+__device__ __forceinline__ double horner3(double A, double B, double C, double D, double s) {
+    return ((A * s + B) * s + C) * s + D;
+}
+
+__device__ inline double refine_root(double A, double B, double C, double D, double sa, double sb, double ga) {
+    double a = sa, b = sb;
+    double x = 0.5 * (a + b);
+    for (int it = 0; it < 64; ++it) {
+        double gx = horner3(A, B, C, D, x);
+        if (gx == 0.0) return x;
+        if ((gx < 0.0) == (ga < 0.0)) { a = x; ga = gx; }
+        else b = x;
+        if (b - a <= 1e-13 * (1.0 + b)) break;
+        double dg = (3.0 * A * x + 2.0 * B) * x + C;
+        double xn = dg != 0.0 ? x - gx / dg : 0.5 * (a + b);
+        if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
+        x = xn;
+    }
+    return 0.5 * (a + b);
+}
+
+__device__ inline void test_cell(const Ray &R, const int c[3], double t0, double t1, const float fc[8], float iso,
+                                 CellHit &res) {
+    res.hit = 0;
+    int above = 0, below = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        above += fc[i] > iso;
+        below += fc[i] < iso;
+    }
+    if (above == 8 || below == 8) return;
+    if (t1 < t0) return;
+    double S = t1 - t0;
+    double al[3][2], be[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double l = (R.o[a] + t0 * R.d[a]) - (double)c[a];
+        res.loc[a] = l;
+        al[a][0] = 1.0 - l;
+        be[a][0] = -R.d[a];
+        al[a][1] = l;
+        be[a][1] = R.d[a];
+    }
+    double A = 0.0, B = 0.0, C = 0.0, D = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        int a = i & 1, b = (i >> 1) & 1, g = (i >> 2) & 1;
+        double ax = al[0][a], bx = be[0][a], ay = al[1][b], by = be[1][b], az = al[2][g], bz = be[2][g];
+        double td = (ax * ay) * az;
+        double tc = ((bx * ay) * az + (ax * by) * az) + (ax * ay) * bz;
+        double tb = ((bx * by) * az + (bx * ay) * bz) + (ax * by) * bz;
+        double ta = (bx * by) * bz;
+        double cv = (double)fc[i];
+        D = D + cv * td;
+        C = C + cv * tc;
+        B = B + cv * tb;
+        A = A + cv * ta;
+    }
+    D = D - (double)iso;
+    double cand0 = -1.0, cand1 = -1.0;
+    if (A != 0.0) {
+        double disc = B * B - (3.0 * A) * C;
+        if (disc >= 0.0) {
+            double q = -(B + copysign(sqrt(disc), B));
+            cand0 = q / (3.0 * A);
+            if (q != 0.0) cand1 = C / q;
+        }
+    } else if (B != 0.0) {
+        cand0 = -C / (2.0 * B);
+    }
+    double e0 = 0.0, e1 = 0.0;
+    int ne = 0;
+    if (cand0 > 0.0 && cand0 < S) { e0 = cand0; ne = 1; }
+    if (cand1 > 0.0 && cand1 < S) {
+        if (ne == 0) { e0 = cand1; ne = 1; }
+        else {
+            if (cand1 < e0) { e1 = e0; e0 = cand1; ne = 2; }
+            else if (cand1 > e0) { e1 = cand1; ne = 2; }
+        }
+    }
+    double pts[4];
+    int np = 0;
+    pts[np++] = 0.0;
+    if (ne >= 1) pts[np++] = e0;
+    if (ne >= 2) pts[np++] = e1;
+    pts[np++] = S;
+    double gp = horner3(A, B, C, D, pts[0]);
+    if (gp == 0.0) { res.hit = 1; res.s = 0.0; return; }
+    for (int i = 1; i < np; ++i) {
+        double gi = horner3(A, B, C, D, pts[i]);
+        if ((gp < 0.0 && gi > 0.0) || (gp > 0.0 && gi < 0.0)) {
+            res.hit = 1;
+            res.s = refine_root(A, B, C, D, pts[i - 1], pts[i], gp);
+            return;
+        }
+        if (gi == 0.0) { res.hit = 1; res.s = pts[i]; return; }
+        gp = gi;
+    }
+}
+
+// Headlight Lambertian shading of the hit: base colour (0.90, 0.75, 0.40) x
+// (0.15 + 0.85 |n.d|), n the normalised trilinear gradient; RGBA8, r low byte.
+__device__ inline uint32_t shade_hit(const Ray &R, const CellHit &h, const float fc[8]) {
+    double u = h.loc[0] + h.s * R.d[0], v = h.loc[1] + h.s * R.d[1], w = h.loc[2] + h.s * R.d[2];
+    double U0 = 1.0 - u, U1 = u, V0 = 1.0 - v, V1 = v, W0 = 1.0 - w, W1 = w;
+    double c[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = (double)fc[i];
+    double gx = ((c[1] - c[0]) * V0 + (c[3] - c[2]) * V1) * W0 + ((c[5] - c[4]) * V0 + (c[7] - c[6]) * V1) * W1;
+    double gy = ((c[2] - c[0]) * U0 + (c[3] - c[1]) * U1) * W0 + ((c[6] - c[4]) * U0 + (c[7] - c[5]) * U1) * W1;
+    double gz = ((c[4] - c[0]) * U0 + (c[5] - c[1]) * U1) * V0 + ((c[6] - c[2]) * U0 + (c[7] - c[3]) * U1) * V1;
+    double len = sqrt((gx * gx + gy * gy) + gz * gz);
+    double nd = len > 0.0 ? fabs((gx * R.d[0] + gy * R.d[1]) + gz * R.d[2]) / len : 1.0;
+    double k = 0.15 + 0.85 * nd;
+    const double base[3] = {0.90, 0.75, 0.40};
+    uint32_t out = 0xFF000000u;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        double x = floor(255.0 * (base[ch] * k) + 0.5);
+        x = x < 0.0 ? 0.0 : (x > 255.0 ? 255.0 : x);
+        out |= (uint32_t)x << (8 * ch);
+    }
+    return out;
+}
+
+// ------------------------------------------------------ host-side hooks --
+// Kernel launchers implemented in the .hip files (all on one stream).
+struct Launch;
+
+}  // namespace spr

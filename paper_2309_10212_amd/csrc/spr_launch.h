@@ -1,0 +1,35 @@
+// spr_launch.h — host-side launchers of the libspr kernels (one stream each).
+#pragma once
+
+#include "spr_internal.h"
+
+namespace spr {
+
+// Fixed launch shapes of a pass; every kernel loops over its device-side
+// count, so one shape serves every pass and the sequence can be replayed as
+// a captured graph.
+struct PassGrids {
+    uint32_t rays;      // 256-thread groups over the active-ray space
+    uint32_t pairs;     // 256-thread groups over the pair space
+    uint32_t blocks;    // 256-thread groups over visible/active/miss lists
+    uint32_t slots;     // 256-thread groups over cache slots (eviction sweeps)
+    uint32_t decode;    // one-wave groups decoding misses
+    uint32_t scatter;   // one-wave groups scattering pairs
+};
+
+hipError_t launch_decode_ids(hipStream_t s, const VolDev &V, const uint32_t *ids, uint32_t n, float *out);
+hipError_t launch_fp64_ops(hipStream_t s, const double *x, const double *y, uint64_t n, double *sq, double *dv);
+hipError_t launch_load_grids(hipStream_t s, const VolDev &V);
+hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t v);
+hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n, uint64_t v);
+hipError_t launch_iota_u32(hipStream_t s, uint32_t *p, uint64_t n);
+hipError_t launch_release_volume(hipStream_t s, PassCtl *ctl, const Cache &C, uint32_t vol);
+hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols);
+constexpr int PASS_KERNELS = 13;
+extern const char *const PASS_KERNEL_NAMES[PASS_KERNELS];
+// ev == nullptr: plain launches; else ev[i] is recorded before kernel i and
+// ev[PASS_KERNELS] after the last one.
+hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, const Work &W,
+                       const Cache &C, const PassGrids &g, hipEvent_t *ev);
+
+}  // namespace spr
