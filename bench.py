@@ -47,11 +47,12 @@ def kernel_bytes(name, c, rate):
     A, S, P, Ps = c["rays"], c["pair_slots"], c["pairs"], c["served_pairs"]
     V, K, M = c["visible_blocks"], c["active_blocks"], c["blocks_decoded"]
     model = {
-        "k_traverse": 8 * A + 4 * S + 32 * V,
+        "k_traverse": 8 * A + 4 * S + 8 * V,
+        "k_dedupe": 4 * S + 8 * P + 20 * V,
         "k_mark": 4 * S + 16 * P + 8 * V + 16 * K,
         "k_lookup": 8 * V + 24 * K + 8 * M,
-        "k_assign": 32 * M,
-        "k_decode_scatter": (8 * rate + 268) * M + 4 * S + 28 * Ps,
+        "k_assign_scatter": 32 * M + 4 * S + 28 * Ps,
+        "k_decode": (8 * rate + 268) * M,
         "k_raytrace": 36 * Ps + 532 * V,
         "k_composite": 8 * A + 4 * S + 20 * P,
         "k_compact": 12 * A,
@@ -113,6 +114,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-views", type=int, default=10)
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
+    ap.add_argument("--batch-reps", type=int, default=3, help="repetitions of the batched orbit (0 = skip)")
+    ap.add_argument("--poll-every", type=int, default=2)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -169,7 +172,7 @@ def main():
     passes = sum(i["passes"] for i in infos)
     value = rays / elapsed
     dev_ms = sum(ms for ms, _ in ktimes.values())
-    dec_ms = ktimes.get("k_decode_scatter", (0.0, 0))[0]
+    dec_ms = ktimes.get("k_decode", (0.0, 0))[0]
 
     # roofline of the dominant kernel (largest device time in the timed region)
     dom = max(ktimes.items(), key=lambda kv: kv[1][0])
@@ -199,6 +202,37 @@ def main():
                           "ms_per_pass": round((s1 - s0) * 1e3 / pp, 4), "ms_per_view": round((s1 - s0) * 1e3 / len(inf), 3),
                           "utilization": round(sum(i["pairs"] for i in inf) / (pp * args.w * args.h), 4)})
             log(f"[bench] sweep cap {cap}: {sweep[-1]}")
+
+    # batched: the 10 orbit views as one batch (one replayed pass advances all
+    # of them), including the grid rebuild and every render's initial rays
+    batched = None
+    if args.batch_reps > 0:
+        def batch_run():
+            vol.build_grids()
+            rs = [spr.Render(vol, cam, iso, args.w, args.h, spec_cap=args.spec_cap) for cam in cams]
+            b = spr.Batch(ctx, rs)
+            npass = b.run(poll_every=args.poll_every)
+            infos_b = [r.info() for r in rs]
+            b.free()
+            for r in rs:
+                r.free()
+            return npass, infos_b
+        batch_run()   # warm-up: graph capture, allocator
+        torch.cuda.synchronize()
+        b0 = time.perf_counter()
+        tot_rays = tot_passes = 0
+        for _ in range(args.batch_reps):
+            npass, inf = batch_run()
+            tot_rays += sum(i["rays_entered"] for i in inf)
+            tot_passes += npass
+        torch.cuda.synchronize()
+        b1 = time.perf_counter()
+        batched = {"requests": len(cams), "reps": args.batch_reps, "rays_per_s": round(tot_rays / (b1 - b0), 1),
+                   "ms_per_batch": round((b1 - b0) * 1e3 / args.batch_reps, 3),
+                   "ms_per_pass": round((b1 - b0) * 1e3 / max(tot_passes, 1), 4),
+                   "passes_per_batch": tot_passes / args.batch_reps,
+                   "vs_plain": round(tot_rays / (b1 - b0) / value, 3)}
+        log(f"[bench] batched: {batched}")
 
     cur, peak = ctx.mem_stats()
     cpu = None
@@ -234,6 +268,7 @@ def main():
         "counters": dc,
         "kernels_ms_per_launch": {k: round(ms / max(nl, 1), 5) for k, (ms, nl) in ktimes.items()},
         "roofline": roof,
+        "batched": batched,
         "sweep": sweep,
         "cpu_baseline": cpu,
     }

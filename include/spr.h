@@ -236,6 +236,15 @@ spr_status spr_render_free(spr_render *r);
  * replayed.  The renders stay owned by the caller and must outlive the batch;
  * each may belong to at most one live batch. */
 spr_status spr_batch_create(spr_ctx *ctx, uint32_t n, spr_render *const *renders, spr_batch **out);
+/* An empty batch with room for max_requests renders totalling max_pixels
+ * pixels (continuous batching: members change with spr_batch_set between
+ * passes while the captured pass is reused). */
+spr_status spr_batch_create_empty(spr_ctx *ctx, uint32_t max_requests, uint64_t max_pixels, spr_batch **out);
+/* Replace the members of a batch (0..capacity renders of the batch's
+ * context; a render may belong to one batch at a time).  Renders keep their
+ * progress when they join or leave.  Synchronises; SPR_E_CAPACITY if the
+ * renders exceed the batch's request or pixel capacity. */
+spr_status spr_batch_set(spr_batch *b, uint32_t n, spr_render *const *renders);
 /* One pass of every unfinished render; synchronises and reports how many
  * renders are still unfinished. */
 spr_status spr_batch_pass(spr_batch *b, uint32_t *n_unfinished);

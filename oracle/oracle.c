@@ -43,7 +43,13 @@
 
 static int bit_at(const uint32_t *w, uint32_t pos) { return (int)((w[pos >> 5] >> (pos & 31)) & 1u); }
 
-static int64_t floor_div2(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
+/* Integer arithmetic of the inverse transform is 32-bit two's complement
+ * (codec format version 1): sums wrap modulo 2^32; halving rounds toward
+ * minus infinity.  Records written by the encoder never wrap (forward
+ * coefficients stay below 2^30); the rule only fixes what a decoder returns
+ * for any other record. */
+static int32_t wrap32(int64_t x) { return (int32_t)(uint32_t)(uint64_t)x; }
+static int32_t floor_div2(int32_t x) { return x >= 0 ? x / 2 : -(int32_t)(((uint32_t)(-(int64_t)x) + 1u) / 2u); }
 
 /* coefficient order: positions sorted by lev(x)+lev(y)+lev(z), lev={0,1,2,2},
  * ties by raster index; computed by brute force over the 64 positions */
@@ -56,14 +62,14 @@ static void coeff_order(int order[64]) {
 }
 
 /* inverse of the 4-point two-level integer S-transform on one line */
-static void inv_line(int64_t *p, int stride) {
-    int64_t L = p[0], H = p[stride], h0 = p[2 * stride], h1 = p[3 * stride];
-    int64_t l1 = L - floor_div2(H);
-    int64_t l0 = l1 + H;
-    int64_t a1 = l0 - floor_div2(h0);
-    int64_t a0 = a1 + h0;
-    int64_t a3 = l1 - floor_div2(h1);
-    int64_t a2 = a3 + h1;
+static void inv_line(int32_t *p, int stride) {
+    int32_t L = p[0], H = p[stride], h0 = p[2 * stride], h1 = p[3 * stride];
+    int32_t l1 = wrap32((int64_t)L - floor_div2(H));
+    int32_t l0 = wrap32((int64_t)l1 + H);
+    int32_t a1 = wrap32((int64_t)l0 - floor_div2(h0));
+    int32_t a0 = wrap32((int64_t)a1 + h0);
+    int32_t a3 = wrap32((int64_t)l1 - floor_div2(h1));
+    int32_t a2 = wrap32((int64_t)a3 + h1);
     p[0] = a0; p[stride] = a1; p[2 * stride] = a2; p[3 * stride] = a3;
 }
 
@@ -115,8 +121,8 @@ int orc_decode_block(const uint32_t *rec, int R, float *out) {
 done:;
     int order[64];
     coeff_order(order);
-    int64_t q[64];
-    for (int j = 0; j < 64; ++j) q[order[j]] = neg[j] ? -(int64_t)mag[j] : (int64_t)mag[j];
+    int32_t q[64];
+    for (int j = 0; j < 64; ++j) q[order[j]] = neg[j] ? -(int32_t)mag[j] : (int32_t)mag[j];   /* mag < 2^30 */
     for (int y = 0; y < 4; ++y) for (int x = 0; x < 4; ++x) inv_line(q + x + 4 * y, 16); /* z */
     for (int z = 0; z < 4; ++z) for (int x = 0; x < 4; ++x) inv_line(q + x + 16 * z, 4); /* y */
     for (int z = 0; z < 4; ++z) for (int y = 0; y < 4; ++y) inv_line(q + 4 * y + 16 * z, 1); /* x */

@@ -91,6 +91,10 @@ struct spr_render {
     bool started = false;       // a pass has run
     spr_batch *batch = nullptr;
     float last_ms = 0.f;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t graph_gen = ~0ull;
+    uint64_t fwords = 0, cwords = 0;   // isovalue mask sizes (u32 words)
 };
 
 struct spr_batch {
@@ -101,6 +105,7 @@ struct spr_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t graph_gen = ~0ull;
+    uint64_t max_pixels = 0;
 };
 
 namespace {
@@ -194,8 +199,9 @@ PassGrids grids_for(const spr_ctx *c, uint64_t max_A, uint64_t max_P) {
     pg.pairs = g(max_P, 256, 2048);
     pg.blocks = g(8 * max_P, 256, 2048);
     pg.slots = g(c->cache.n_slots, 256, 2048);
-    pg.decode = 2048;
-    pg.scatter = g(max_P, 64, 4096);
+    pg.assign = 256;
+    pg.scatter = g(max_P, 256, 2048);
+    pg.decode = g(8 * max_P, 64, 4096);
     return pg;
 }
 
@@ -220,22 +226,29 @@ spr_status ensure_work(spr_ctx *c, uint64_t P) {
     return SPR_OK;
 }
 
-spr_status alloc_table(spr_ctx *c, uint32_t nreq, uint64_t max_A, uint64_t max_P, Table &T) {
-    T.nreq = nreq;
+spr_status alloc_table(spr_ctx *c, uint32_t cap, uint64_t max_A, uint64_t max_P, Table &T) {
+    T.cap = cap;
     T.max_A = (uint32_t)max_A;
     T.max_P = (uint32_t)max_P;
-    CHK(dalloc(c, nreq + 1, &T.act_base));
-    CHK(dalloc(c, nreq + 1, &T.pair_base));
+    CHK(dalloc(c, 1, &T.hdr));
+    CHK(dalloc(c, cap + 1, &T.act_base));
+    CHK(dalloc(c, cap + 1, &T.pair_base));
     CHK(dalloc(c, max_A / 64 + 2, &T.wave_cnt));
     CHK(dalloc(c, max_A / 64 + 2, &T.wave_off));
     return SPR_OK;
 }
 
 void free_table(spr_ctx *c, Table &T) {
-    dfree(c, T.act_base, T.nreq + 1);
-    dfree(c, T.pair_base, T.nreq + 1);
+    dfree(c, T.hdr, 1);
+    dfree(c, T.act_base, T.cap + 1);
+    dfree(c, T.pair_base, T.cap + 1);
     dfree(c, T.wave_cnt, T.max_A / 64 + 2);
     dfree(c, T.wave_off, T.max_A / 64 + 2);
+}
+
+spr_status set_table_count(spr_ctx *c, Table &T, uint32_t n) {
+    HIPCHK(hipMemcpy(T.hdr, &n, sizeof(n), hipMemcpyHostToDevice));
+    return SPR_OK;
 }
 
 spr_status read_state(spr_ctx *c, const ReqState *d, ReqState *h) {
@@ -249,6 +262,29 @@ spr_status read_ctl(spr_ctx *c, PassCtl *h) {
     HIPCHK(hipMemcpyAsync((char *)c->pinned + 256, c->ctl, sizeof(PassCtl), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     memcpy(h, (char *)c->pinned + 256, sizeof(PassCtl));
+    return SPR_OK;
+}
+
+// One pass of a launch table replayed from a captured graph (recorded on the
+// private capture stream, since the context stream may be the null stream).
+spr_status graph_pass(spr_ctx *c, const Table &T, const PassGrids &g, hipGraph_t &graph, hipGraphExec_t &exec,
+                      uint64_t &gen) {
+    if (gen != c->work_gen || !exec) {
+        if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
+        if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = launch_pass(c->cap_stream, c->ctl, T, c->d_vols, c->work, c->cache, g, nullptr);
+        hipGraph_t gr = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return fail(SPR_E_HIP, "pass capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        graph = gr;
+        HIPCHK(hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0));
+        gen = c->work_gen;
+    }
+    HIPCHK(hipGraphLaunch(exec, c->stream));
     return SPR_OK;
 }
 
@@ -604,6 +640,8 @@ static void free_render_buffers(spr_ctx *c, spr_render *r) {
     dfree(c, q.hits, n);
     dfree(c, r->d_st, 1);
     dfree(c, r->d_req, 1);
+    dfree(c, q.fmask, r->fwords);
+    dfree(c, q.cmask, r->cwords);
     free_table(c, r->table);
 }
 
@@ -642,6 +680,13 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
         if ((st = dalloc(c, npix, &q.hits)) != SPR_OK) break;
         if ((st = dalloc(c, 1, &r->d_st)) != SPR_OK) break;
         if ((st = dalloc(c, 1, &r->d_req)) != SPR_OK) break;
+        {
+            const VolDev &V = c->h_vols[v->idx];
+            r->fwords = (V.nblocks + 31) / 32;
+            r->cwords = ((uint64_t)V.nc[0] * V.nc[1] * V.nc[2] + 31) / 32;
+        }
+        if ((st = dalloc(c, r->fwords, &q.fmask)) != SPR_OK) break;
+        if ((st = dalloc(c, r->cwords, &q.cmask)) != SPR_OK) break;
         if ((st = alloc_table(c, 1, round64h(npix), npix, r->table)) != SPR_OK) break;
         st = ensure_work(c, npix);
     } while (0);
@@ -656,9 +701,11 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     ReqState s0{};
     s0.n_act = (uint32_t)npix;
     s0.cur = 1;
+    const uint32_t one = 1;
     hipError_t e = hipMemcpy(r->d_st, &s0, sizeof(s0), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(r->table.hdr, &one, sizeof(one), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r->d_req, &q, sizeof(q), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols);
+    if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols, r->fwords + r->cwords);
     if (e != hipSuccess) {
         free_render_buffers(c, r);
         delete r;
@@ -718,7 +765,8 @@ spr_status spr_render_pass(spr_render *r, spr_pass_stats *stats) {
     spr_ctx *c = r->ctx;
     HIPCHK(hipSetDevice(c->device));
     if (stats) HIPCHK(hipEventRecord(c->ev0, c->stream));
-    CHK(run_pass(c, r->table, r->grids));
+    if (c->prof) CHK(run_pass(c, r->table, r->grids));
+    else CHK(graph_pass(c, r->table, r->grids, r->graph, r->exec, r->graph_gen));
     r->started = true;
     if (stats) {
         HIPCHK(hipEventRecord(c->ev1, c->stream));
@@ -743,15 +791,35 @@ spr_status spr_render_done(spr_render *r, int *done) {
 spr_status spr_render_run(spr_render *r, uint32_t max_passes, uint32_t *passes_run) {
     if (!r) return fail(SPR_E_INVALID, "null render");
     if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
-    uint32_t n = 0;
-    int done = 0;
-    CHK(spr_render_done(r, &done));
-    while (!done && n < max_passes) {
-        CHK(spr_render_pass(r, nullptr));
-        ++n;
-        CHK(spr_render_done(r, &done));
+    spr_ctx *c = r->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    ReqState s0;
+    CHK(read_state(c, r->d_st, &s0));
+    const uint32_t start = s0.passes;
+    // Keep two passes in flight: after enqueuing pass i+1, wait for pass i's
+    // copy of N_act.  A pass on a finished render does no work, so the one
+    // pass that may run past completion costs only its empty launches.
+    const int DEPTH = 2;
+    hipEvent_t ev[DEPTH] = {c->ev0, c->ev1};
+    volatile uint32_t *flag = (volatile uint32_t *)((char *)c->pinned + 3840);   // clear of the other staging areas
+    uint32_t enq = 0, waited = 0;
+    bool done = s0.n_act == 0;
+    while (!done) {
+        while (enq < max_passes && enq - waited < (uint32_t)DEPTH) {
+            CHK(spr_render_pass(r, nullptr));
+            HIPCHK(hipMemcpyAsync((void *)(flag + (enq % DEPTH)), &r->d_st->n_act, 4, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipEventRecord(ev[enq % DEPTH], c->stream));
+            ++enq;
+        }
+        if (waited == enq) break;   // max_passes reached
+        HIPCHK(hipEventSynchronize(ev[waited % DEPTH]));
+        done = flag[waited % DEPTH] == 0;
+        ++waited;
     }
-    if (passes_run) *passes_run = n;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    ReqState s1;
+    CHK(read_state(c, r->d_st, &s1));
+    if (passes_run) *passes_run = s1.passes - start;
     return SPR_OK;
 }
 
@@ -805,6 +873,8 @@ spr_status spr_render_free(spr_render *r) {
     spr_ctx *c = r->ctx;
     HIPCHK(hipSetDevice(c->device));
     HIPCHK(hipStreamSynchronize(c->stream));
+    if (r->exec) (void)hipGraphExecDestroy(r->exec);
+    if (r->graph) (void)hipGraphDestroy(r->graph);
     free_render_buffers(c, r);
     r->vol->n_renders--;
     c->n_renders--;
@@ -814,75 +884,84 @@ spr_status spr_render_free(spr_render *r) {
 
 // ------------------------------------------------------------------ batch --
 
-spr_status spr_batch_create(spr_ctx *c, uint32_t n, spr_render *const *renders, spr_batch **out) {
-    if (!c || !out || (n && !renders)) return fail(SPR_E_INVALID, "null argument");
+spr_status spr_batch_create_empty(spr_ctx *c, uint32_t max_requests, uint64_t max_pixels, spr_batch **out) {
+    if (!c || !out) return fail(SPR_E_INVALID, "null argument");
     *out = nullptr;
-    if (n == 0 || n > MAX_REQS) return fail(SPR_E_INVALID, "batch size must be 1..%d", MAX_REQS);
-    uint64_t A = 0, P = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        spr_render *r = renders[i];
-        if (!r || r->ctx != c) return fail(SPR_E_INVALID, "render %u is null or from another context", i);
-        if (r->batch) return fail(SPR_E_STATE, "render %u already belongs to a batch", i);
-        for (uint32_t j = 0; j < i; ++j)
-            if (renders[j] == r) return fail(SPR_E_INVALID, "render %u listed twice", i);
-        A += round64h(r->npix);
-        P += r->npix;
-    }
-    if (A >= 0xFFFFFFFFull || P > 0xFFFFFFFFull / 8) return fail(SPR_E_INVALID, "batch too large");
+    if (max_requests == 0 || max_requests > MAX_REQS) return fail(SPR_E_INVALID, "batch capacity must be 1..%d", MAX_REQS);
+    uint64_t A = max_pixels + 64ull * max_requests, P = max_pixels;
+    if (A >= 0xFFFFFFFFull || P > 0xFFFFFFFFull / 8 || max_pixels == 0) return fail(SPR_E_INVALID, "bad pixel capacity");
     HIPCHK(hipSetDevice(c->device));
     spr_batch *b = new (std::nothrow) spr_batch();
     if (!b) return fail(SPR_E_OOM, "host allocation failed");
     b->ctx = c;
-    b->renders.assign(renders, renders + n);
-    spr_status st = alloc_table(c, n, A, P, b->table);
-    if (st == SPR_OK) st = dalloc(c, n, &b->table.reqs);
+    b->max_pixels = max_pixels;
+    spr_status st = alloc_table(c, max_requests, A, P, b->table);
+    if (st == SPR_OK) st = dalloc(c, max_requests, &b->table.reqs);
     if (st == SPR_OK) st = ensure_work(c, P);
+    if (st == SPR_OK) st = set_table_count(c, b->table, 0);
     if (st != SPR_OK) {
         free_table(c, b->table);
-        dfree(c, b->table.reqs, n);
+        dfree(c, b->table.reqs, max_requests);
         delete b;
         return st;
     }
+    b->grids = grids_for(c, A, P);
+    *out = b;
+    return SPR_OK;
+}
+
+spr_status spr_batch_set(spr_batch *b, uint32_t n, spr_render *const *renders) {
+    if (!b || (n && !renders)) return fail(SPR_E_INVALID, "null argument");
+    spr_ctx *c = b->ctx;
+    if (n > b->table.cap) return fail(SPR_E_CAPACITY, "%u renders exceed the batch capacity %u", n, b->table.cap);
+    uint64_t pix = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        spr_render *r = renders[i];
+        if (!r || r->ctx != c) return fail(SPR_E_INVALID, "render %u is null or from another context", i);
+        if (r->batch && r->batch != b) return fail(SPR_E_STATE, "render %u belongs to another batch", i);
+        for (uint32_t j = 0; j < i; ++j)
+            if (renders[j] == r) return fail(SPR_E_INVALID, "render %u listed twice", i);
+        pix += r->npix;
+    }
+    if (pix > b->max_pixels) return fail(SPR_E_CAPACITY, "renders need %llu pixels, batch holds %llu",
+                                         (unsigned long long)pix, (unsigned long long)b->max_pixels);
+    HIPCHK(hipSetDevice(c->device));
     std::vector<ReqDev> reqs(n);
     for (uint32_t i = 0; i < n; ++i) reqs[i] = renders[i]->hreq;
-    hipError_t e = hipMemcpy(b->table.reqs, reqs.data(), n * sizeof(ReqDev), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        free_table(c, b->table);
-        dfree(c, b->table.reqs, n);
-        delete b;
-        return fail(SPR_E_HIP, "batch set-up failed: %s", hipGetErrorString(e));
-    }
-    b->grids = grids_for(c, A, P);
+    // stream-ordered: passes already enqueued see the old table
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (n) HIPCHK(hipMemcpy(b->table.reqs, reqs.data(), n * sizeof(ReqDev), hipMemcpyHostToDevice));
+    CHK(set_table_count(c, b->table, n));
+    for (auto *r : b->renders) r->batch = nullptr;
+    b->renders.assign(renders, renders + n);
     for (auto *r : b->renders) r->batch = b;
+    return SPR_OK;
+}
+
+spr_status spr_batch_create(spr_ctx *c, uint32_t n, spr_render *const *renders, spr_batch **out) {
+    if (!c || !out || (n && !renders)) return fail(SPR_E_INVALID, "null argument");
+    *out = nullptr;
+    if (n == 0 || n > MAX_REQS) return fail(SPR_E_INVALID, "batch size must be 1..%d", MAX_REQS);
+    uint64_t P = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!renders[i] || renders[i]->ctx != c) return fail(SPR_E_INVALID, "render %u is null or from another context", i);
+        P += renders[i]->npix;
+    }
+    spr_batch *b = nullptr;
+    CHK(spr_batch_create_empty(c, n, P, &b));
+    spr_status st = spr_batch_set(b, n, renders);
+    if (st != SPR_OK) {
+        spr_batch_free(b);
+        return st;
+    }
     *out = b;
     return SPR_OK;
 }
 
 static spr_status batch_launch(spr_batch *b) {
     spr_ctx *c = b->ctx;
-    if (c->prof) {
-        CHK(run_pass(c, b->table, b->grids));
-        for (auto *r : b->renders) r->started = true;
-        return SPR_OK;
-    }
-    if (b->graph_gen != c->work_gen) {
-        if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
-        // record on the private stream (the context stream may be the null
-        // stream, which cannot be captured); replays go to the context stream
-        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = launch_pass(c->cap_stream, c->ctl, b->table, c->d_vols, c->work, c->cache, b->grids, nullptr);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
-        if (e != hipSuccess || e2 != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return fail(SPR_E_HIP, "pass capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
-        }
-        b->graph = g;
-        HIPCHK(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
-        b->graph_gen = c->work_gen;
-    }
-    HIPCHK(hipGraphLaunch(b->exec, c->stream));
+    if (c->prof) CHK(run_pass(c, b->table, b->grids));
+    else CHK(graph_pass(c, b->table, b->grids, b->graph, b->exec, b->graph_gen));
     for (auto *r : b->renders) r->started = true;
     return SPR_OK;
 }
@@ -890,6 +969,11 @@ static spr_status batch_launch(spr_batch *b) {
 static spr_status batch_unfinished(spr_batch *b, uint32_t *n_unfinished) {
     spr_ctx *c = b->ctx;
     uint32_t n = (uint32_t)b->renders.size();
+    if (n == 0) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        *n_unfinished = 0;
+        return SPR_OK;
+    }
     char *dst = (char *)c->pinned + 1024;
     if (n * sizeof(uint32_t) > 2048) {
         // large batches: read in chunks through the staging area
@@ -950,7 +1034,7 @@ spr_status spr_batch_free(spr_batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     free_table(c, b->table);
-    dfree(c, b->table.reqs, b->renders.size());
+    dfree(c, b->table.reqs, b->table.cap);
     for (auto *r : b->renders) r->batch = nullptr;
     delete b;
     return SPR_OK;

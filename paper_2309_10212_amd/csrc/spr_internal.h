@@ -81,6 +81,8 @@ struct ReqDev {
     uint32_t *image;            // RGBA8 per pixel
     spr_hit *hits;              // per pixel
     ReqState *st;
+    uint32_t *fmask;            // per block: fine range contains iso (1 bit, by block id)
+    uint32_t *cmask;            // per coarse cell: coarse range contains iso
 };
 
 // Per-pass control block of a context (counters reset at each pass start).
@@ -118,12 +120,14 @@ struct PassCtl {
 
 // Launch table of a pass: the requests advanced together.
 struct Table {
-    ReqDev *reqs;               // nreq entries
-    uint32_t *act_base;         // nreq+1, 64-aligned prefix of n_act
-    uint32_t *pair_base;        // nreq+1, prefix of n_act*n_spec
+    ReqDev *reqs;               // up to cap entries
+    uint32_t *hdr;              // hdr[0] = current number of requests (device-resident,
+                                // so membership can change between graph replays)
+    uint32_t *act_base;         // cap+1, 64-aligned prefix of n_act
+    uint32_t *pair_base;        // cap+1, prefix of n_act*n_spec
     uint32_t *wave_cnt;         // survivors per 64-entry wave of the A space
     uint32_t *wave_off;
-    uint32_t nreq;
+    uint32_t cap;               // request capacity
     uint32_t max_A;             // capacity of the A space (sum of padded npix)
     uint32_t max_P;             // capacity of the pair space (sum of npix)
 };
@@ -419,23 +423,24 @@ __device__ inline void test_cell(const Ray &R, const int c[3], double t0, double
             else if (cand1 > e0) { e1 = cand1; ne = 2; }
         }
     }
-    double pts[4];
-    int np = 0;
-    pts[np++] = 0.0;
-    if (ne >= 1) pts[np++] = e0;
-    if (ne >= 2) pts[np++] = e1;
-    pts[np++] = S;
-    double gp = horner3(A, B, C, D, pts[0]);
+    // ordered points {0, e0 (ne >= 1), e1 (ne == 2), S}: first exact zero or
+    // strict sign change wins
+    double sp = 0.0;
+    double gp = horner3(A, B, C, D, 0.0);
     if (gp == 0.0) { res.hit = 1; res.s = 0.0; return; }
-    for (int i = 1; i < np; ++i) {
-        double gi = horner3(A, B, C, D, pts[i]);
-        if ((gp < 0.0 && gi > 0.0) || (gp > 0.0 && gi < 0.0)) {
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+        if (k > ne + 1) break;
+        const double sk = k == ne + 1 ? S : (k == 1 ? e0 : e1);
+        const double gk = horner3(A, B, C, D, sk);
+        if ((gp < 0.0 && gk > 0.0) || (gp > 0.0 && gk < 0.0)) {
             res.hit = 1;
-            res.s = refine_root(A, B, C, D, pts[i - 1], pts[i], gp);
+            res.s = refine_root(A, B, C, D, sp, sk, gp);
             return;
         }
-        if (gi == 0.0) { res.hit = 1; res.s = pts[i]; return; }
-        gp = gi;
+        if (gk == 0.0) { res.hit = 1; res.s = sk; return; }
+        sp = sk;
+        gp = gk;
     }
 }
 

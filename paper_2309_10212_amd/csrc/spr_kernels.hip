@@ -30,148 +30,228 @@ static constexpr OrderTable make_order() {
 
 __constant__ OrderTable c_order = make_order();
 
-// ----------------------------------------------------- codec: wave decode --
-// One wave decodes one block; lane j owns the coefficient at position j of
-// the embedded order.  The bit-plane control state (read position, plane,
-// significance mask, cursor) is wave-uniform; the refinement bits are read in
-// parallel (lane rank among the significant set = mbcnt of the mask); the
-// group-test scan finds the first set bit of a 64-bit window (ctz) and the
-// target coefficient as the z-th candidate (rank by mbcnt).  The inverse
-// integer transform runs on 64-bit integers in LDS, z then y then x.
+// --------------------------------------------------- codec: thread decode --
+// One thread decodes one block, bit by bit, in the order the format defines
+// (the same control flow as the encoder, mirrored).  The record words sit in
+// registers and the next word is picked by an unrolled select (no dynamic
+// register indexing); magnitudes of the order-space coefficients live in LDS,
+// interleaved so that a wave touching coefficient j hits 64 distinct banks;
+// the significance mask and the sign mask are 64-bit registers.  The inverse
+// integer transform then runs on 64 int32 values in registers with
+// compile-time indices.
 
-__device__ __forceinline__ uint32_t rec_word(const uint32_t *s_rec, int rw, int i) {
-    return i < rw ? s_rec[i] : 0u;
+static constexpr OrderTable kOrder = make_order();
+
+template <int RWMAX>
+__device__ __forceinline__ uint32_t pick_word(const uint32_t (&w)[RWMAX], uint32_t i) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < RWMAX; ++j) r = (uint32_t)j == i ? w[j] : r;
+    return r;
 }
 
-__device__ __forceinline__ uint64_t window64(const uint32_t *s_rec, int rw, uint32_t p) {
-    int i = (int)(p >> 5);
-    uint32_t sh = p & 31u;
-    uint64_t ab = (uint64_t)rec_word(s_rec, rw, i) | ((uint64_t)rec_word(s_rec, rw, i + 1) << 32);
-    if (sh == 0) return ab;
-    return (ab >> sh) | ((uint64_t)rec_word(s_rec, rw, i + 2) << (64 - sh));
+// 32-bit two's complement lifting (the codec's integer arithmetic): sums
+// wrap modulo 2^32 (done in unsigned arithmetic), halving is an arithmetic
+// shift (rounds toward minus infinity).
+__device__ __forceinline__ int32_t half32(int32_t x) { return x >> 1; }
+__device__ __forceinline__ int32_t add32(int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); }
+__device__ __forceinline__ int32_t sub32(int32_t a, int32_t b) { return (int32_t)((uint32_t)a - (uint32_t)b); }
+
+__device__ __forceinline__ void inv4(int32_t &p0, int32_t &p1, int32_t &p2, int32_t &p3) {
+    int32_t L = p0, H = p1, h0 = p2, h1 = p3;
+    int32_t l1 = sub32(L, half32(H));
+    int32_t l0 = add32(l1, H);
+    int32_t a1 = sub32(l0, half32(h0));
+    int32_t a0 = add32(a1, h0);
+    int32_t a3 = sub32(l1, half32(h1));
+    int32_t a2 = add32(a3, h1);
+    p0 = a0; p1 = a1; p2 = a2; p3 = a3;
 }
 
-__device__ __forceinline__ int64_t floor_half64(int64_t x) { return x >> 1; }
-
-__device__ __forceinline__ void inv_line64(int64_t *p, int stride) {
-    int64_t L = p[0], H = p[stride], h0 = p[2 * stride], h1 = p[3 * stride];
-    int64_t l1 = L - floor_half64(H);
-    int64_t l0 = l1 + H;
-    int64_t a1 = l0 - floor_half64(h0);
-    int64_t a0 = a1 + h0;
-    int64_t a3 = l1 - floor_half64(h1);
-    int64_t a2 = a3 + h1;
-    p[0] = a0; p[stride] = a1; p[2 * stride] = a2; p[3 * stride] = a3;
-}
-
-// Requires a workgroup of exactly one wave (uses __syncthreads as the wave
-// barrier).  Returns this lane's decoded value at raster index lane.
-__device__ float wave_decode(const uint32_t *rec, int rate, int rw, uint32_t *s_rec, int64_t *s_q) {
-    const uint32_t l = lane_id();
-    if (rate == 32) return __uint_as_float(rec[l]);
-    if ((int)l < rw) s_rec[l] = rec[l];
-    __syncthreads();
-    const uint32_t w0 = __builtin_amdgcn_readfirstlane(s_rec[0]);
-    float result = 0.0f;
-    if (w0 & 1u) {
-        const int e = (int)((w0 >> 1) & 0xFFu) - 127;
-        const uint32_t B = 64u * (uint32_t)rate;
-        const uint64_t below = lanemask_lt();
-        uint32_t pos = 9;
-        uint64_t S = 0;
-        uint32_t mag = 0, neg = 0;
-        for (int k = 29; k >= 0; --k) {
-            // refinement bits, one per coefficient significant before this plane
-            uint32_t n = (uint32_t)__popcll(S);
-            uint32_t avail = B - pos < n ? B - pos : n;
-            if (n) {
-                uint64_t win = window64(s_rec, rw, pos);
-                uint32_t r = (uint32_t)__popcll(S & below);
-                if (((S >> l) & 1ull) && r < avail) mag |= (uint32_t)((win >> r) & 1ull) << k;
-            }
-            pos += avail;
-            if (avail < n) break;
-            // significance pass: group tests from the cursor
+// Decodes the record into q[64] (raster order) and the block exponent.
+// Returns false for an all-zero block (q untouched).  s_mag: this wave's
+// 64x64 u32 LDS area; lane: lane id within the wave.
+template <int RWMAX>
+__device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, int rate, uint32_t *s_mag,
+                                              uint32_t lane, int32_t (&q)[64], int &e_out) {
+    const uint32_t rw = 2u * (uint32_t)rate;
+    uint32_t w[RWMAX];
+#pragma unroll
+    for (int j = 0; j < RWMAX; ++j) w[j] = (uint32_t)j < rw ? rec[j] : 0u;
+    if (!(w[0] & 1u)) return false;
+    e_out = (int)((w[0] >> 1) & 0xFFu) - 127;
+    const uint32_t B = 64u * (uint32_t)rate;
+    uint64_t buf = ((uint64_t)w[0] | ((uint64_t)w[1] << 32)) >> 9;
+    uint32_t nbits = 55, wi = 2, pos = 9;
+    uint64_t S = 0, NEG = 0;
+#define SPR_READBIT(dst)                                            \
+    do {                                                            \
+        dst = (uint32_t)(buf & 1ull);                               \
+        buf >>= 1;                                                  \
+        --nbits;                                                    \
+        ++pos;                                                      \
+        if (nbits < 32) {                                           \
+            buf |= (uint64_t)pick_word<RWMAX>(w, wi) << nbits;      \
+            nbits += 32;                                            \
+            ++wi;                                                   \
+        }                                                           \
+    } while (0)
+    for (int k = 29; k >= 0; --k) {
+        // refinement: one bit per coefficient significant before this plane
+        uint64_t m = S;
+        while (m) {
+            if (pos >= B) goto done;
+            uint32_t b;
+            SPR_READBIT(b);
+            uint32_t j = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+            m &= m - 1ull;
+            if (b) s_mag[j * 64 + lane] |= 1u << k;
+        }
+        // significance: group tests over the insignificant ones from cursor c
+        {
             uint32_t c = 0;
-            bool stop = false;
             for (;;) {
                 uint64_t I = c >= 64 ? 0ull : (~S & (~0ull << c));
                 if (I == 0) break;
-                if (pos >= B) { stop = true; break; }
-                uint32_t g = (uint32_t)(window64(s_rec, rw, pos) & 1ull);
-                pos++;
+                if (pos >= B) goto done;
+                uint32_t g;
+                SPR_READBIT(g);
                 if (!g) break;
-                uint32_t ncand = (uint32_t)__popcll(I);
-                uint32_t lim = B - pos < ncand ? B - pos : ncand;
-                uint64_t win = window64(s_rec, rw, pos);
-                if (lim < 64) win &= (1ull << lim) - 1ull;
-                if (win == 0) { stop = true; break; }
-                uint32_t z = (uint32_t)__ffsll((unsigned long long)win) - 1u;
-                pos += z + 1;
-                // target = the z-th candidate (0-based) of I
-                bool inI = (I >> l) & 1ull;
-                uint32_t rk = (uint32_t)__popcll(I & below);
-                uint64_t tm = __ballot(inI && rk == z);
-                uint32_t target = (uint32_t)__ffsll((unsigned long long)tm) - 1u;
-                if (pos >= B) { stop = true; break; }
-                uint32_t sgn = (uint32_t)(window64(s_rec, rw, pos) & 1ull);
-                pos++;
-                if (l == target) { mag |= 1u << k; neg = sgn; }
-                S |= 1ull << target;
-                c = target + 1;
+                int t = -1;
+                while (I) {
+                    if (pos >= B) goto done;
+                    uint32_t b;
+                    SPR_READBIT(b);
+                    int j = __ffsll((unsigned long long)I) - 1;
+                    I &= I - 1ull;
+                    if (b) { t = j; break; }
+                }
+                if (t < 0) goto done;
+                if (pos >= B) goto done;
+                uint32_t sg;
+                SPR_READBIT(sg);
+                NEG |= (uint64_t)sg << t;
+                s_mag[(uint32_t)t * 64 + lane] = 1u << k;
+                S |= 1ull << t;
+                c = (uint32_t)t + 1;
             }
-            if (stop) break;
         }
-        int64_t cval = neg ? -(int64_t)mag : (int64_t)mag;
-        s_q[c_order.ord[l]] = cval;
-        __syncthreads();
-        if (l < 16) inv_line64(s_q + (l & 3) + 4 * (l >> 2), 16);   // z lines
-        __syncthreads();
-        if (l < 16) inv_line64(s_q + (l & 3) + 16 * (l >> 2), 4);   // y lines
-        __syncthreads();
-        if (l < 16) inv_line64(s_q + 4 * (l & 3) + 16 * (l >> 2), 1);   // x lines
-        __syncthreads();
-        result = (float)ldexp((double)s_q[l], e - 27);
     }
-    __syncthreads();
-    return result;
+done:
+#undef SPR_READBIT
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+        int32_t v = 0;   // magnitudes are below 2^30
+        if ((S >> j) & 1ull) {
+            v = (int32_t)s_mag[j * 64 + lane];
+            if ((NEG >> j) & 1ull) v = -v;
+        }
+        q[kOrder.ord[j]] = v;
+    }
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) inv4(q[x + 4 * y], q[x + 4 * y + 16], q[x + 4 * y + 32], q[x + 4 * y + 48]);
+#pragma unroll
+    for (int z = 0; z < 4; ++z)
+#pragma unroll
+        for (int x = 0; x < 4; ++x) inv4(q[x + 16 * z], q[x + 16 * z + 4], q[x + 16 * z + 8], q[x + 16 * z + 12]);
+#pragma unroll
+    for (int z = 0; z < 4; ++z)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) inv4(q[4 * y + 16 * z], q[4 * y + 16 * z + 1], q[4 * y + 16 * z + 2], q[4 * y + 16 * z + 3]);
+    return true;
+}
+
+// Decode one block to 64 floats, stored with 16-byte stores to dst (raster order).
+template <int RWMAX>
+__device__ __forceinline__ void decode_to(const uint32_t *__restrict__ rec, int rate, uint32_t *s_mag, uint32_t lane,
+                                          float *__restrict__ dst) {
+    float4 *d4 = reinterpret_cast<float4 *>(dst);
+    if (rate == 32) {
+        const float4 *s4 = reinterpret_cast<const float4 *>(rec);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) d4[i] = s4[i];
+        return;
+    }
+    int32_t q[64];
+    int e = 0;
+    if (!thread_decode<RWMAX>(rec, rate, s_mag, lane, q, e)) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) d4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    if (e >= -99) {
+        // every nonzero value is a normal float: (float)q then an exact
+        // power-of-two scale equals the single rounding of q * 2^(e-27)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            d4[i] = make_float4(ldexpf((float)q[4 * i], e - 27), ldexpf((float)q[4 * i + 1], e - 27),
+                                ldexpf((float)q[4 * i + 2], e - 27), ldexpf((float)q[4 * i + 3], e - 27));
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            d4[i] = make_float4((float)ldexp((double)q[4 * i], e - 27), (float)ldexp((double)q[4 * i + 1], e - 27),
+                                (float)ldexp((double)q[4 * i + 2], e - 27), (float)ldexp((double)q[4 * i + 3], e - 27));
+    }
 }
 
 // --------------------------------------------------------- decode kernels --
 
 // Decode listed blocks of one volume into out[i*64 ..] (debug/parity path).
 __global__ __launch_bounds__(64) void k_decode_ids(VolDev V, const uint32_t *ids, uint32_t n, float *out) {
-    __shared__ uint32_t s_rec[64];
-    __shared__ int64_t s_q[64];
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    __shared__ uint32_t s_mag[64 * 64];
+    const uint32_t lane = threadIdx.x;
+    for (uint32_t i = blockIdx.x * 64 + lane; i < n; i += gridDim.x * 64) {
         const uint32_t *rec = V.stream + (size_t)ids[i] * (size_t)V.rec_words;
-        float v = wave_decode(rec, V.rate, V.rec_words, s_rec, s_q);
-        out[(size_t)i * 64 + lane_id()] = v;
+        decode_to<32>(rec, V.rate, s_mag, lane, out + (size_t)i * 64);
     }
 }
 
 // Load path: decode every block once and keep only its value range over the
 // samples inside the volume (Sec. 3.1).
+template <int RWMAX>
 __global__ __launch_bounds__(64) void k_block_ranges(VolDev V, float2 *blk) {
-    __shared__ uint32_t s_rec[64];
-    __shared__ int64_t s_q[64];
-    const uint32_t l = lane_id();
-    for (uint64_t b = blockIdx.x; b < V.nblocks; b += gridDim.x) {
+    __shared__ uint32_t s_mag[64 * 64];
+    const uint32_t lane = threadIdx.x;
+    for (uint64_t b = blockIdx.x * 64ull + lane; b < V.nblocks; b += (uint64_t)gridDim.x * 64) {
         const uint32_t *rec = V.stream + b * (uint64_t)V.rec_words;
-        float v = wave_decode(rec, V.rate, V.rec_words, s_rec, s_q);
         int bx = (int)(b % (uint64_t)V.nb[0]);
         int by = (int)((b / (uint64_t)V.nb[0]) % (uint64_t)V.nb[1]);
         int bz = (int)(b / ((uint64_t)V.nb[0] * V.nb[1]));
-        int x = 4 * bx + (int)(l & 3), y = 4 * by + (int)((l >> 2) & 3), z = 4 * bz + (int)(l >> 4);
-        bool in = x < V.n[0] && y < V.n[1] && z < V.n[2];
-        float lo = in ? v : __builtin_inff(), hi = in ? v : -__builtin_inff();
+        int ex = V.n[0] - 4 * bx, ey = V.n[1] - 4 * by, ez = V.n[2] - 4 * bz;   // samples inside, per axis
+        float lo = __builtin_inff(), hi = -__builtin_inff();
+        if (V.rate == 32) {
+            const float4 *f4 = reinterpret_cast<const float4 *>(rec);
+            for (int i4 = 0; i4 < 16; ++i4) {
+                float4 v4 = f4[i4];
+                float vv[4] = {v4.x, v4.y, v4.z, v4.w};
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            float ol = __shfl_xor(lo, off), oh = __shfl_xor(hi, off);
-            lo = ol < lo ? ol : lo;
-            hi = oh > hi ? oh : hi;
+                for (int c = 0; c < 4; ++c) {
+                    int i = 4 * i4 + c;
+                    bool in = c < ex && ((i >> 2) & 3) < ey && (i >> 4) < ez;
+                    if (in) { lo = vv[c] < lo ? vv[c] : lo; hi = vv[c] > hi ? vv[c] : hi; }
+                }
+            }
+        } else {
+            int32_t q[64];
+            int e = 0;
+            if (!thread_decode<RWMAX>(rec, V.rate, s_mag, lane, q, e)) {
+                lo = 0.0f;
+                hi = 0.0f;
+            } else {
+                // conversion to float is monotone: reduce the integers, convert two
+                int32_t qlo = 0x7FFFFFFF, qhi = (int32_t)0x80000000;
+#pragma unroll
+                for (int i = 0; i < 64; ++i) {
+                    bool in = (i & 3) < ex && ((i >> 2) & 3) < ey && (i >> 4) < ez;
+                    if (in) { qlo = q[i] < qlo ? q[i] : qlo; qhi = q[i] > qhi ? q[i] : qhi; }
+                }
+                lo = (float)ldexp((double)qlo, e - 27);
+                hi = (float)ldexp((double)qhi, e - 27);
+            }
         }
-        if (l == 0) blk[b] = make_float2(lo, hi);
+        blk[b] = make_float2(lo, hi);
     }
 }
 
@@ -284,8 +364,9 @@ __global__ void k_pass_begin(PassCtl *ctl, Table T, int is_init) {
     ctl->n_vis = 0; ctl->v_adm = 0; ctl->n_actblk = 0; ctl->n_miss = 0; ctl->n_hit = 0;
     ctl->cursor = 0; ctl->served = 0; ctl->deferred = 0; ctl->need = 0; ctl->evict_T = 64;
     ctl->evict_done_blocks = 0; ctl->evicted = 0; ctl->terminated = 0; ctl->pairs = 0; ctl->overflow = 0;
+    const uint32_t nreq = T.hdr[0];
     uint32_t A = 0, P = 0, rays = 0;
-    for (uint32_t r = 0; r < T.nreq; ++r) {
+    for (uint32_t r = 0; r < nreq; ++r) {
         ReqState *st = T.reqs[r].st;
         uint32_t na = st->n_act, ns = st->n_spec;
         T.act_base[r] = A;
@@ -302,12 +383,45 @@ __global__ void k_pass_begin(PassCtl *ctl, Table T, int is_init) {
         rays += na;
     }
     ctl->rays = rays;
-    T.act_base[T.nreq] = A;
-    T.pair_base[T.nreq] = P;
+    T.act_base[nreq] = A;
+    T.pair_base[nreq] = P;
     ctl->A = A;
     ctl->P = P;
-    ctl->nreq = T.nreq;
+    ctl->nreq = nreq;
 }
+
+// ----------------------------------------------------------- isovalue masks --
+// Per request, one bit per block (fine grid) and per coarse cell: the range
+// contains the isovalue (inclusive, compared in float32, exactly the test the
+// traversal needs).  256 KB for 2M blocks: the traversal's per-step test then
+// hits L2 instead of the 8-byte ranges.
+__global__ void k_iso_masks(Table T, const VolDev *vols) {
+    const ReqDev &q = T.reqs[0];
+    const VolDev &V = vols[q.vol];
+    const float iso = q.iso;
+    const uint64_t nfw = (V.nblocks + 31) / 32;
+    const uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    const uint64_t ncw = (nc + 31) / 32;
+    for (uint64_t wdx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; wdx < nfw + ncw;
+         wdx += (uint64_t)gridDim.x * blockDim.x) {
+        bool coarse = wdx >= nfw;
+        uint64_t w0 = (coarse ? wdx - nfw : wdx) * 32;
+        uint64_t lim = coarse ? nc : V.nblocks;
+        const float2 *rng = coarse ? V.coarse : V.fine;
+        uint32_t bits = 0;
+        for (int i = 0; i < 32; ++i) {
+            uint64_t id = w0 + i;
+            if (id < lim) {
+                float2 r = rng[id];
+                bits |= (uint32_t)(r.x <= iso && iso <= r.y) << i;
+            }
+        }
+        if (coarse) q.cmask[wdx - nfw] = bits;
+        else q.fmask[wdx] = bits;
+    }
+}
+
+__device__ __forceinline__ bool mask_bit(const uint32_t *m, uint64_t id) { return (m[id >> 5] >> (id & 31)) & 1u; }
 
 // ------------------------------------------------------------ initial rays --
 // Sec. 3.2: one thread per pixel computes the ray and its volume entry; rays
@@ -316,7 +430,8 @@ __global__ void k_pass_begin(PassCtl *ctl, Table T, int is_init) {
 __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
     uint32_t A = ctl->A;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
-        uint32_t r = find_req(T.act_base, T.nreq, p);
+        // all lanes of a wave share a request (the A space is 64-aligned per request)
+        uint32_t r = __builtin_amdgcn_readfirstlane(find_req(T.act_base, ctl->nreq, p));
         const ReqDev &q = T.reqs[r];
         uint32_t i = p - T.act_base[r];
         bool alive = false;
@@ -344,15 +459,15 @@ __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
 // walks the coarse grid, descends into coarse cells whose range contains the
 // isovalue and walks their blocks, and records up to N_spec blocks whose fine
 // range contains the isovalue at slots i*N_spec + k; unused slots get NONE.
-// First visitors of a block append it to the visible list (stamp dedupe).
+// The walk does no atomics: visible-block dedupe runs in its own kernel.
 
 __device__ __forceinline__ bool range_has(float2 r, float iso) { return r.x <= iso && iso <= r.y; }
 
-__global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const VolDev *vols, Work W) {
+__global__ __launch_bounds__(256, 5) void k_traverse(PassCtl *ctl, Table T, const VolDev *vols) {
     const uint32_t A = ctl->A;
-    const uint32_t pass = ctl->pass;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
-        uint32_t r = find_req(T.act_base, T.nreq, p);
+        // all lanes of a wave share a request (the A space is 64-aligned per request)
+        uint32_t r = __builtin_amdgcn_readfirstlane(find_req(T.act_base, ctl->nreq, p));
         const ReqDev &q = T.reqs[r];
         const ReqState *st = q.st;
         uint32_t i = p - T.act_base[r];
@@ -362,7 +477,6 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         const VolDev &V = vols[q.vol];
         Ray R;
         make_ray(q, V.n, pix, R);
-        const float iso = q.iso;
         uint32_t *slots = q.pair_blk + (size_t)i * ns;
         Level LB = {4, {V.tb[0], V.tb[1], V.tb[2]}, {V.n[0], V.n[1], V.n[2]}};
         Level LC = {16, {V.tc[0], V.tc[1], V.tc[2]}, {V.n[0], V.n[1], V.n[2]}};
@@ -404,7 +518,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
             if (++steps > max_steps) { alive = false; break; }   // every step advances an index
             if (ctest) {
                 const uint64_t cid = ((uint64_t)cc[2] * V.nc[1] + cc[1]) * V.nc[0] + cc[0];
-                if (range_has(V.coarse[cid], iso)) {
+                if (mask_bit(q.cmask, cid)) {
                     if (!bvalid) {
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
@@ -424,19 +538,10 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                 }
             }
             const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * V.nb[1] + cb[1]) * V.nb[0] + cb[0]);
-            const bool emit = range_has(V.fine[bid], iso);
+            const bool emit = mask_bit(q.fmask, bid);
             if (emit) {
                 slots[found] = bid;
                 found++;
-                bool first = false;
-                if (__hip_atomic_load(&V.vis_stamp[bid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pass)
-                    first = atomicExch(&V.vis_stamp[bid], pass) != pass;
-                uint32_t idx = wave_append(&ctl->n_vis, first);
-                if (first) {
-                    W.vis_list[idx] = ((uint64_t)q.vol << 32) | bid;
-                    V.vis_idx[bid] = idx;
-                    W.vis_cnt[idx] = 0;
-                }
                 if (found == ns) break;
             }
             double tn = cell_exit(R, LB, cb);
@@ -449,6 +554,37 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
             }
         }
         for (uint32_t k = found; k < ns; ++k) slots[k] = NONE;
+    }
+}
+
+// --------------------------------------------------------------- K1b ------
+// Visible blocks (Sec. 3.4): one thread per pair slot; the first visitor of a
+// block in this pass (per-block pass stamp) appends it to the visible list
+// and records its index; its pair count starts at 0.
+__global__ __launch_bounds__(256) void k_dedupe(PassCtl *ctl, Table T, const VolDev *vols, Work W) {
+    const uint32_t P = ctl->P;
+    const uint32_t pass = ctl->pass;
+    for (uint32_t x0 = blockIdx.x * blockDim.x; x0 < P; x0 += gridDim.x * blockDim.x) {
+        const uint32_t x = x0 + threadIdx.x;
+        bool first = false;
+        uint32_t b = NONE, vol = 0;
+        if (x < P) {
+            uint32_t r = find_req(T.pair_base, ctl->nreq, x);
+            const ReqDev &q = T.reqs[r];
+            b = q.pair_blk[x - T.pair_base[r]];
+            vol = q.vol;
+            if (b != NONE) {
+                uint32_t *stp = &vols[vol].vis_stamp[b];
+                if (__hip_atomic_load(stp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pass)
+                    first = atomicExch(stp, pass) != pass;
+            }
+        }
+        uint32_t idx = wave_append(&ctl->n_vis, first);
+        if (first) {
+            W.vis_list[idx] = ((uint64_t)vol << 32) | b;
+            vols[vol].vis_idx[b] = idx;
+            W.vis_cnt[idx] = 0;
+        }
     }
 }
 
@@ -473,7 +609,7 @@ __global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, Table T, const VolDe
     uint32_t n_served = 0, n_def = 0;
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += stride) {
         if (x < P) {
-            uint32_t r = find_req(T.pair_base, T.nreq, x);
+            uint32_t r = find_req(T.pair_base, ctl->nreq, x);
             const ReqDev &q = T.reqs[r];
             uint32_t b = q.pair_blk[x - T.pair_base[r]];
             if (b != NONE) {
@@ -622,55 +758,36 @@ __global__ __launch_bounds__(256) void k_evict(PassCtl *ctl, const VolDev *vols,
 }
 
 // ---------------------------------------------------------------- K5 ------
-// Assign the top n_miss free slots to the misses.
-__global__ __launch_bounds__(256) void k_assign(PassCtl *ctl, const VolDev *vols, Work W, Cache C) {
-    const uint32_t f = ctl->free_top;
-    uint32_t m = ctl->n_miss;
-    if (m > f) m = f;   // cannot happen: admission keeps the active blocks within n_slots
-    const uint32_t base = f - m;
-    const uint32_t pass = ctl->pass;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->assigned = m;
-        if (m < ctl->n_miss) ctl->overflow = 1;
-    }
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-        uint64_t e = W.miss_list[i];
-        uint32_t s = C.free_stack[base + i];
-        vols[(uint32_t)(e >> 32)].map[(uint32_t)e] = s;
-        C.owner[s] = e;
-        C.stamp[s] = pass;
-        W.miss_slot[i] = s;
-    }
-}
-
-// ---------------------------------------------------------------- K6 ------
-// Role A (waves 0 .. dec_groups-1): decode misses into their slots (Sec. 3.5).
-// Role B (other workgroups): scatter served pairs into their block's run
+// Role A (first assign_groups workgroups): hand the top n_miss free slots to
+// the misses.  Role B (the rest): scatter served pairs into their block's run
 // (the sort by block id of Sec. 3.6 / 4.2; the pair slot carries O_Spec).
-__global__ __launch_bounds__(64) void k_decode_scatter(PassCtl *ctl, Table T, const VolDev *vols, Work W, Cache C,
-                                                       uint32_t dec_groups) {
-    __shared__ uint32_t s_rec[64];
-    __shared__ int64_t s_q[64];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // the slots handed out by k_assign leave the free stack
-        ctl->free_top -= ctl->assigned;
-    }
-    if (blockIdx.x < dec_groups) {
-        const uint32_t m = ctl->assigned;
-        for (uint32_t i = blockIdx.x; i < m; i += dec_groups) {
+__global__ __launch_bounds__(256) void k_assign_scatter(PassCtl *ctl, Table T, const VolDev *vols, Work W, Cache C,
+                                                        uint32_t assign_groups) {
+    if (blockIdx.x < assign_groups) {
+        const uint32_t f = ctl->free_top;
+        uint32_t m = ctl->n_miss;
+        if (m > f) m = f;   // cannot happen: admission keeps the active blocks within n_slots
+        const uint32_t base = f - m;
+        const uint32_t pass = ctl->pass;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl->assigned = m;
+            if (m < ctl->n_miss) ctl->overflow = 1;
+        }
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += assign_groups * blockDim.x) {
             uint64_t e = W.miss_list[i];
-            const VolDev &V = vols[(uint32_t)(e >> 32)];
-            const uint32_t *rec = V.stream + (uint64_t)(uint32_t)e * (uint64_t)V.rec_words;
-            float v = wave_decode(rec, V.rate, V.rec_words, s_rec, s_q);
-            C.slots[(size_t)W.miss_slot[i] * 64 + lane_id()] = v;
+            uint32_t sl = C.free_stack[base + i];
+            vols[(uint32_t)(e >> 32)].map[(uint32_t)e] = sl;
+            C.owner[sl] = e;
+            C.stamp[sl] = pass;
+            W.miss_slot[i] = sl;
         }
         return;
     }
     const uint32_t P = ctl->P;
     const uint32_t vadm = admitted_blocks(ctl);
-    const uint32_t nthreads = (gridDim.x - dec_groups) * blockDim.x;
-    for (uint32_t x = (blockIdx.x - dec_groups) * blockDim.x + threadIdx.x; x < P; x += nthreads) {
-        uint32_t r = find_req(T.pair_base, T.nreq, x);
+    const uint32_t nthreads = (gridDim.x - assign_groups) * blockDim.x;
+    for (uint32_t x = (blockIdx.x - assign_groups) * blockDim.x + threadIdx.x; x < P; x += nthreads) {
+        uint32_t r = find_req(T.pair_base, ctl->nreq, x);
         const ReqDev &q = T.reqs[r];
         uint32_t qq = x - T.pair_base[r];
         uint32_t b = q.pair_blk[qq];
@@ -687,6 +804,21 @@ __global__ __launch_bounds__(64) void k_decode_scatter(PassCtl *ctl, Table T, co
     }
 }
 
+// ---------------------------------------------------------------- K6 ------
+// Decode the misses into their slots (Sec. 3.5), one thread per block.
+__global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols, Work W, Cache C) {
+    __shared__ uint32_t s_mag[64 * 64];
+    const uint32_t m = ctl->assigned;
+    for (uint32_t i = blockIdx.x * 64 + threadIdx.x; i < m; i += gridDim.x * 64) {
+        uint64_t e = W.miss_list[i];
+        const VolDev &V = vols[(uint32_t)(e >> 32)];
+        const uint32_t *rec = V.stream + (uint64_t)(uint32_t)e * (uint64_t)V.rec_words;
+        decode_to<32>(rec, V.rate, s_mag, threadIdx.x, C.slots + (size_t)W.miss_slot[i] * 64);
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->free_top -= m;   // the assigned slots leave the free stack
+}
+
 // ---------------------------------------------------------------- K9 ------
 // Block raytrace (Sec. 3.7, 4.3): each served pair walks its ray through the
 // dual cells of its block (Amanatides-Woo restricted to the block), tests
@@ -699,67 +831,149 @@ __device__ __forceinline__ float slot_value(const float *slots, const uint32_t n
     return slots[(size_t)s * 64 + ((lx & 3) + 4 * (ly & 3) + 16 * (lz & 3))];
 }
 
-__global__ __launch_bounds__(256) void k_raytrace(PassCtl *ctl, Table T, const VolDev *vols, Work W, Cache C) {
+// A 256-pair tile of the sorted pairs covers runs of a few blocks.  The
+// workgroup stages the 5^3 dual grid of each distinct block of the tile
+// (up to RT_LB blocks) into LDS once - the block's 4^3 samples plus the +x/+y/
+// +z face, edge and corner samples of its neighbours (Sec. 3.7) - and every
+// pair then reads its cell corners from LDS.  Pairs of blocks beyond RT_LB in
+// a tile read the slots directly.
+constexpr int RT_TILE = 256;
+constexpr int RT_LB = 32;
+
+__global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, const VolDev *vols, Work W, Cache C) {
+    __shared__ float s_grid[RT_LB][128];
+    __shared__ uint32_t s_nsl[RT_LB][8];
+    __shared__ int s_bb[RT_LB][4];
+    __shared__ uint32_t s_scan[RT_TILE / 64];
+    __shared__ uint32_t s_nloc;
     const uint32_t n = ctl->served;
-    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
-        uint32_t ray = W.s_ray[j];
-        uint32_t r = ray >> 24, pix = ray & 0xFFFFFFu;
-        uint32_t qq = W.s_q[j];
-        uint64_t e = W.vis_list[W.s_vi[j]];
-        const ReqDev &q = T.reqs[r];
-        const VolDev &V = vols[(uint32_t)(e >> 32)];
-        uint32_t b = (uint32_t)e;
-        int bb[3];
-        bb[0] = (int)(b % (uint32_t)V.nb[0]);
-        bb[1] = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
-        bb[2] = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
-        uint32_t nsl[8];
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            int x2 = bb[0] + (o & 1), y2 = bb[1] + ((o >> 1) & 1), z2 = bb[2] + (o >> 2);
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t base = blockIdx.x * RT_TILE; base < n; base += gridDim.x * RT_TILE) {
+        const uint32_t j = base + tid;
+        const bool valid = j < n;
+        const uint32_t vi = valid ? W.s_vi[j] : NONE;
+        const uint32_t prev = (valid && tid > 0) ? W.s_vi[j - 1] : NONE;
+        const bool start = valid && (tid == 0 || vi != prev);
+        // workgroup exclusive scan of run starts -> local block index
+        uint64_t m = __ballot(start);
+        uint32_t wrank = (uint32_t)__popcll(m & lanemask_lt());
+        if (lane_id() == 0) s_scan[tid >> 6] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t woff = 0, tot = 0;
+        for (uint32_t w = 0; w < RT_TILE / 64; ++w) {
+            uint32_t c = s_scan[w];
+            if (w < (tid >> 6)) woff += c;
+            tot += c;
+        }
+        // lb of this pair = (number of run starts at or before it) - 1
+        uint32_t lb = woff + wrank + (start ? 1u : 0u) - 1u;
+        {
+            // pairs that are not starts: lb = starts before them - 1 (same as above minus nothing)
+            uint32_t before = woff + wrank;   // starts strictly before this lane
+            lb = start ? before : before - 1u;
+        }
+        const uint32_t nloc = tot < (uint32_t)RT_LB ? tot : (uint32_t)RT_LB;
+        if (start && lb < (uint32_t)RT_LB) {
+            uint64_t e = W.vis_list[vi];
+            const VolDev &V = vols[(uint32_t)(e >> 32)];
+            uint32_t b = (uint32_t)e;
+            s_bb[lb][0] = (int)(b % (uint32_t)V.nb[0]);
+            s_bb[lb][1] = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
+            s_bb[lb][2] = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
+            s_bb[lb][3] = (int)(uint32_t)(e >> 32);
+        }
+        __syncthreads();
+        // slots of the 8 blocks of each staged block's 2x2x2 neighbourhood
+        for (uint32_t x = tid; x < nloc * 8; x += RT_TILE) {
+            uint32_t l = x >> 3, o = x & 7;
+            const VolDev &V = vols[s_bb[l][3]];
+            int x2 = s_bb[l][0] + (o & 1), y2 = s_bb[l][1] + ((o >> 1) & 1), z2 = s_bb[l][2] + (o >> 2);
             bool ok = x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2];
-            nsl[o] = ok ? V.map[((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2] : 0u;
+            s_nsl[l][o] = ok ? V.map[((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2] : NONE;
         }
-        Ray R;
-        make_ray(q, V.n, pix, R);
-        Level LB = {4, {V.tb[0], V.tb[1], V.tb[2]}, {V.n[0], V.n[1], V.n[2]}};
-        Level L1 = {1, {V.n[0] - 1, V.n[1] - 1, V.n[2] - 1}, {V.n[0], V.n[1], V.n[2]}};
-        int lo[3], hi[3], c[3];
-        double tb0 = cell_entry(R, LB, bb);
+        __syncthreads();
+        // stage the 5^3 dual grids
+        for (uint32_t x = tid; x < nloc * 125; x += RT_TILE) {
+            uint32_t l = x / 125, k = x - l * 125;
+            int lx = (int)(k % 5), ly = (int)((k / 5) % 5), lz = (int)(k / 25);
+            int o = (lx >> 2) | ((ly >> 2) << 1) | ((lz >> 2) << 2);
+            uint32_t sl = s_nsl[l][o];
+            s_grid[l][k] = sl == NONE ? 0.0f : C.slots[(size_t)sl * 64 + ((lx & 3) + 4 * (ly & 3) + 16 * (lz & 3))];
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t ray = W.s_ray[j];
+            uint32_t r = ray >> 24, pix = ray & 0xFFFFFFu;
+            uint32_t qq = W.s_q[j];
+            const ReqDev &q = T.reqs[r];
+            const VolDev &V = vols[q.vol];
+            int bb[3];
+            uint32_t nsl[8];
+            const bool staged = lb < (uint32_t)RT_LB;
+            if (staged) {
+                bb[0] = s_bb[lb][0]; bb[1] = s_bb[lb][1]; bb[2] = s_bb[lb][2];
+            } else {
+                uint32_t b = (uint32_t)W.vis_list[vi];
+                bb[0] = (int)(b % (uint32_t)V.nb[0]);
+                bb[1] = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
+                bb[2] = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = 4 * bb[a];
-            hi[a] = 4 * bb[a] + 3;
-            if (hi[a] > V.n[a] - 2) hi[a] = V.n[a] - 2;
-            c[a] = cell_at(R, L1, a, tb0, lo[a], hi[a]);
-        }
-        Rgbz out;
-        out.t = __builtin_inf();
-        out.cell = NONE;
-        out.rgba = 0u;
-        for (int guard = 0; guard < 16; ++guard) {   // at most 10 cells of a 4^3 block lie on a ray
-            double t0 = cell_entry(R, L1, c);
-            double t1 = R.tx;
-            {
-                double x = cell_exit(R, L1, c);
-                if (x < t1) t1 = x;
+                for (int o = 0; o < 8; ++o) {
+                    int x2 = bb[0] + (o & 1), y2 = bb[1] + ((o >> 1) & 1), z2 = bb[2] + (o >> 2);
+                    bool ok = x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2];
+                    nsl[o] = ok ? V.map[((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2] : NONE;
+                }
             }
-            float fc[8];
-            int lx = c[0] - lo[0], ly = c[1] - lo[1], lz = c[2] - lo[2];
+            Ray R;
+            make_ray(q, V.n, pix, R);
+            Level LB = {4, {V.tb[0], V.tb[1], V.tb[2]}, {V.n[0], V.n[1], V.n[2]}};
+            Level L1 = {1, {V.n[0] - 1, V.n[1] - 1, V.n[2] - 1}, {V.n[0], V.n[1], V.n[2]}};
+            int lo[3], hi[3], c[3];
+            double tb0 = cell_entry(R, LB, bb);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) fc[k] = slot_value(C.slots, nsl, lx + (k & 1), ly + ((k >> 1) & 1), lz + (k >> 2));
-            CellHit h;
-            test_cell(R, c, t0, t1, fc, q.iso, h);
-            if (h.hit) {
-                out.t = t0 + h.s;
-                out.cell = (uint32_t)(lx + 4 * ly + 16 * lz);
-                out.rgba = shade_hit(R, h, fc);
-                break;
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = 4 * bb[a];
+                hi[a] = 4 * bb[a] + 3;
+                if (hi[a] > V.n[a] - 2) hi[a] = V.n[a] - 2;
+                c[a] = cell_at(R, L1, a, tb0, lo[a], hi[a]);
             }
-            double tn = cell_exit(R, L1, c);
-            if (tn > R.tx || !advance(R, L1, c, tn, lo, hi)) break;
+            Rgbz out;
+            out.t = __builtin_inf();
+            out.cell = NONE;
+            out.rgba = 0u;
+            for (int guard = 0; guard < 16; ++guard) {   // at most 10 cells of a 4^3 block lie on a ray
+                double t0 = cell_entry(R, L1, c);
+                double t1 = R.tx;
+                {
+                    double x = cell_exit(R, L1, c);
+                    if (x < t1) t1 = x;
+                }
+                float fc[8];
+                int lx = c[0] - lo[0], ly = c[1] - lo[1], lz = c[2] - lo[2];
+                if (staged) {
+                    const float *g = s_grid[lb];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        fc[k] = g[(lx + (k & 1)) + 5 * (ly + ((k >> 1) & 1)) + 25 * (lz + (k >> 2))];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        fc[k] = slot_value(C.slots, nsl, lx + (k & 1), ly + ((k >> 1) & 1), lz + (k >> 2));
+                }
+                CellHit h;
+                test_cell(R, c, t0, t1, fc, q.iso, h);
+                if (h.hit) {
+                    out.t = t0 + h.s;
+                    out.cell = (uint32_t)(lx + 4 * ly + 16 * lz);
+                    out.rgba = shade_hit(R, h, fc);
+                    break;
+                }
+                double tn = cell_exit(R, L1, c);
+                if (tn > R.tx || !advance(R, L1, c, tn, lo, hi)) break;
+            }
+            q.rgbz[qq] = out;
         }
-        q.rgbz[qq] = out;
+        __syncthreads();   // the next tile reuses the LDS
     }
 }
 
@@ -775,7 +989,8 @@ __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const 
     const uint32_t A = ctl->A;
     const uint32_t vadm = admitted_blocks(ctl);
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
-        uint32_t r = find_req(T.act_base, T.nreq, p);
+        // all lanes of a wave share a request (the A space is 64-aligned per request)
+        uint32_t r = __builtin_amdgcn_readfirstlane(find_req(T.act_base, ctl->nreq, p));
         const ReqDev &q = T.reqs[r];
         ReqState *st = q.st;
         uint32_t i = p - T.act_base[r];
@@ -888,7 +1103,7 @@ __global__ __launch_bounds__(1024) void k_pass_end(PassCtl *ctl, Table T, int is
         }
     }
     __syncthreads();
-    for (uint32_t r = t; r < T.nreq; r += blockDim.x) {
+    for (uint32_t r = t; r < ctl->nreq; r += blockDim.x) {
         ReqDev &q = T.reqs[r];
         ReqState *st = q.st;
         uint32_t w0 = T.act_base[r] >> 6, w1 = T.act_base[r + 1] >> 6;
@@ -910,7 +1125,8 @@ __global__ __launch_bounds__(1024) void k_pass_end(PassCtl *ctl, Table T, int is
 __global__ __launch_bounds__(256) void k_compact(PassCtl *ctl, Table T) {
     const uint32_t A = ctl->A;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
-        uint32_t r = find_req(T.act_base, T.nreq, p);
+        // all lanes of a wave share a request (the A space is 64-aligned per request)
+        uint32_t r = __builtin_amdgcn_readfirstlane(find_req(T.act_base, ctl->nreq, p));
         const ReqDev &q = T.reqs[r];
         const ReqState *st = q.st;
         uint32_t i = p - T.act_base[r];
@@ -946,7 +1162,7 @@ static inline uint32_t grid_for(uint64_t n, uint32_t bs, uint32_t cap) {
 }
 
 hipError_t launch_decode_ids(hipStream_t s, const VolDev &V, const uint32_t *ids, uint32_t n, float *out) {
-    hipLaunchKernelGGL(k_decode_ids, dim3(grid_for(n, 1, 65536)), dim3(64), 0, s, V, ids, n, out);
+    hipLaunchKernelGGL(k_decode_ids, dim3(grid_for(n, 64, 8192)), dim3(64), 0, s, V, ids, n, out);
     return hipGetLastError();
 }
 
@@ -956,7 +1172,11 @@ hipError_t launch_fp64_ops(hipStream_t s, const double *x, const double *y, uint
 }
 
 hipError_t launch_load_grids(hipStream_t s, const VolDev &V) {
-    hipLaunchKernelGGL(k_block_ranges, dim3(grid_for(V.nblocks, 1, 1u << 20)), dim3(64), 0, s, V, V.blk);
+    dim3 g(grid_for(V.nblocks, 64, 1u << 16)), b(64);
+    if (V.rec_words <= 4) hipLaunchKernelGGL(k_block_ranges<4>, g, b, 0, s, V, V.blk);
+    else if (V.rec_words <= 8) hipLaunchKernelGGL(k_block_ranges<8>, g, b, 0, s, V, V.blk);
+    else if (V.rec_words <= 16) hipLaunchKernelGGL(k_block_ranges<16>, g, b, 0, s, V, V.blk);
+    else hipLaunchKernelGGL(k_block_ranges<32>, g, b, 0, s, V, V.blk);
     hipLaunchKernelGGL(k_fine_grid, dim3(grid_for(V.nblocks, 256, 1u << 16)), dim3(256), 0, s, V);
     uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
     hipLaunchKernelGGL(k_coarse_grid, dim3(grid_for(nc, 256, 1u << 16)), dim3(256), 0, s, V);
@@ -983,7 +1203,8 @@ hipError_t launch_release_volume(hipStream_t s, PassCtl *ctl, const Cache &C, ui
     return hipGetLastError();
 }
 
-hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols) {
+hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words) {
+    hipLaunchKernelGGL(k_iso_masks, dim3(grid_for(mask_words, 256, 8192)), dim3(256), 0, s, T, vols);
     hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, ctl, T, 1);
     hipLaunchKernelGGL(k_init_rays, dim3(grid_for(T.max_A, 256, 16384)), dim3(256), 0, s, ctl, T, vols);
     hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, s, ctl, T, 1);
@@ -992,8 +1213,8 @@ hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const V
 }
 
 const char *const PASS_KERNEL_NAMES[PASS_KERNELS] = {
-    "k_pass_begin", "k_traverse", "k_mark", "k_lookup", "k_alloc_plan", "k_evict_hist", "k_evict",
-    "k_assign", "k_decode_scatter", "k_raytrace", "k_composite", "k_pass_end", "k_compact"};
+    "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_alloc_plan", "k_evict_hist", "k_evict",
+    "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact"};
 
 hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, const Work &W,
                        const Cache &C, const PassGrids &g, hipEvent_t *ev) {
@@ -1003,15 +1224,16 @@ hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev
         ++k;
     };
     mark(); hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, ctl, T, 0);
-    mark(); hipLaunchKernelGGL(k_traverse, dim3(g.rays), dim3(256), 0, s, ctl, T, vols, W);
+    mark(); hipLaunchKernelGGL(k_traverse, dim3(g.rays), dim3(256), 0, s, ctl, T, vols);
+    mark(); hipLaunchKernelGGL(k_dedupe, dim3(g.pairs), dim3(256), 0, s, ctl, T, vols, W);
     mark(); hipLaunchKernelGGL(k_mark, dim3(g.pairs), dim3(256), 0, s, ctl, T, vols, W);
     mark(); hipLaunchKernelGGL(k_lookup, dim3(g.blocks), dim3(256), 0, s, ctl, vols, W, C);
     mark(); hipLaunchKernelGGL(k_alloc_plan, dim3(1), dim3(64), 0, s, ctl);
     mark(); hipLaunchKernelGGL(k_evict_hist, dim3(g.slots), dim3(256), 0, s, ctl, C);
     mark(); hipLaunchKernelGGL(k_evict, dim3(g.slots), dim3(256), 0, s, ctl, vols, C);
-    mark(); hipLaunchKernelGGL(k_assign, dim3(g.blocks), dim3(256), 0, s, ctl, vols, W, C);
-    mark(); hipLaunchKernelGGL(k_decode_scatter, dim3(g.decode + g.scatter), dim3(64), 0, s, ctl, T, vols, W, C, g.decode);
-    mark(); hipLaunchKernelGGL(k_raytrace, dim3(g.pairs), dim3(256), 0, s, ctl, T, vols, W, C);
+    mark(); hipLaunchKernelGGL(k_assign_scatter, dim3(g.assign + g.scatter), dim3(256), 0, s, ctl, T, vols, W, C, g.assign);
+    mark(); hipLaunchKernelGGL(k_decode, dim3(g.decode), dim3(64), 0, s, ctl, vols, W, C);
+    mark(); hipLaunchKernelGGL(k_raytrace, dim3(g.pairs), dim3(RT_TILE), 0, s, ctl, T, vols, W, C);
     mark(); hipLaunchKernelGGL(k_composite, dim3(g.rays), dim3(256), 0, s, ctl, T, vols);
     mark(); hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, s, ctl, T, 0);
     mark(); hipLaunchKernelGGL(k_compact, dim3(g.rays), dim3(256), 0, s, ctl, T);

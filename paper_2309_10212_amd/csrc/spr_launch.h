@@ -13,8 +13,9 @@ struct PassGrids {
     uint32_t pairs;     // 256-thread groups over the pair space
     uint32_t blocks;    // 256-thread groups over visible/active/miss lists
     uint32_t slots;     // 256-thread groups over cache slots (eviction sweeps)
-    uint32_t decode;    // one-wave groups decoding misses
-    uint32_t scatter;   // one-wave groups scattering pairs
+    uint32_t assign;    // 256-thread groups assigning slots to misses
+    uint32_t scatter;   // 256-thread groups scattering pairs
+    uint32_t decode;    // 64-thread groups decoding misses (one thread per block)
 };
 
 hipError_t launch_decode_ids(hipStream_t s, const VolDev &V, const uint32_t *ids, uint32_t n, float *out);
@@ -24,8 +25,9 @@ hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t v);
 hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n, uint64_t v);
 hipError_t launch_iota_u32(hipStream_t s, uint32_t *p, uint64_t n);
 hipError_t launch_release_volume(hipStream_t s, PassCtl *ctl, const Cache &C, uint32_t vol);
-hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols);
-constexpr int PASS_KERNELS = 13;
+// Isovalue masks of the table's first request, then the initial-ray pass.
+hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words);
+constexpr int PASS_KERNELS = 14;
 extern const char *const PASS_KERNEL_NAMES[PASS_KERNELS];
 // ev == nullptr: plain launches; else ev[i] is recorded before kernel i and
 // ev[PASS_KERNELS] after the last one.

@@ -119,6 +119,8 @@ SIGNATURES = [
     ("spr_render_device_ptrs", _ST, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     ("spr_render_free", _ST, [_P]),
     ("spr_batch_create", _ST, [_P, _U32, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    ("spr_batch_create_empty", _ST, [_P, _U32, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    ("spr_batch_set", _ST, [_P, _U32, ctypes.POINTER(_P)]),
     ("spr_batch_pass", _ST, [_P, ctypes.POINTER(_U32)]),
     ("spr_batch_run", _ST, [_P, _U32, _U32, ctypes.POINTER(_U32)]),
     ("spr_batch_free", _ST, [_P]),
@@ -356,15 +358,31 @@ class Render:
 
 
 class Batch:
-    """Many renders advanced together, one captured pass per call (spr_batch)."""
+    """Many renders advanced together, one captured pass per call (spr_batch).
 
-    def __init__(self, ctx: Context, renders):
+    Batch(ctx, renders) fixes capacity to the given renders; Batch(ctx,
+    max_requests=..., max_pixels=...) creates an empty batch whose members
+    change with set() (continuous batching)."""
+
+    def __init__(self, ctx: Context, renders=None, max_requests: int = 0, max_pixels: int = 0):
         self.ctx = ctx
-        self.renders = list(renders)
-        arr = (ctypes.c_void_p * len(self.renders))(*[r.h_ for r in self.renders])
         h = ctypes.c_void_p()
-        _chk(load_library().spr_batch_create(ctx.h, len(self.renders), arr, ctypes.byref(h)), "spr_batch_create")
+        if renders is not None:
+            self.renders = list(renders)
+            arr = (ctypes.c_void_p * len(self.renders))(*[r.h_ for r in self.renders])
+            _chk(load_library().spr_batch_create(ctx.h, len(self.renders), arr, ctypes.byref(h)),
+                 "spr_batch_create")
+        else:
+            self.renders = []
+            _chk(load_library().spr_batch_create_empty(ctx.h, max_requests, max_pixels, ctypes.byref(h)),
+                 "spr_batch_create_empty")
         self.h = h
+
+    def set(self, renders):
+        rs = list(renders)
+        arr = (ctypes.c_void_p * max(len(rs), 1))(*[r.h_ for r in rs])
+        _chk(load_library().spr_batch_set(self.h, len(rs), arr), "spr_batch_set")
+        self.renders = rs
 
     def pass_(self) -> int:
         n = ctypes.c_uint32()

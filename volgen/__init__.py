@@ -51,6 +51,8 @@ def _load():
         lib.vg_kth_value.argtypes = [P, ctypes.c_size_t, ctypes.c_size_t, P]
         lib.vg_encode.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
         lib.vg_encode_block.argtypes = [P, ctypes.c_int, P]
+        lib.vg_rm_field.argtypes = [ctypes.c_int] * 3 + [ctypes.c_uint64, ctypes.c_double, P]
+        lib.vg_rm_encode.argtypes = [ctypes.c_int] * 3 + [ctypes.c_uint64, ctypes.c_double, ctypes.c_int, P]
         lib.vg_splitmix64.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
         lib.vg_splitmix64.restype = ctypes.c_uint64
         _lib = lib
@@ -88,6 +90,20 @@ def analytic(nx: int, ny: int, nz: int, kind: str, params) -> np.ndarray:
     p[: len(params)] = params
     out = np.empty((nz, ny, nx), np.float32)
     _check(_load().vg_analytic(nx, ny, nz, k, _ptr(p), _ptr(out)), "analytic")
+    return out
+
+
+def rm_field(nx: int, ny: int, nz: int, seed: int = 3, hsum: float = 120.0) -> np.ndarray:
+    """RM-like mixing-layer field, values 0..255 as float32 (small sizes)."""
+    out = np.empty((nz, ny, nx), np.float32)
+    _check(_load().vg_rm_field(nx, ny, nz, seed, hsum, _ptr(out)), "rm_field")
+    return out
+
+
+def rm_encode(nx: int, ny: int, nz: int, rate: int, seed: int = 3, hsum: float = 120.0) -> np.ndarray:
+    """Generate and compress the RM-like field block by block (no full buffer)."""
+    out = np.zeros(stream_bytes(nx, ny, nz, rate), np.uint8)
+    _check(_load().vg_rm_encode(nx, ny, nz, seed, hsum, rate, _ptr(out)), "rm_encode")
     return out
 
 

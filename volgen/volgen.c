@@ -214,6 +214,204 @@ int vg_quantize_u8(float *vals, size_t n, float lo, float hi) {
     return VG_OK;
 }
 
+/* --------------------------------------------- RM-like mixing layer --- */
+/* A two-fluid interface at mid-depth shaped like a Richtmyer-Meshkov mixing
+ * layer:  v = clamp(round(255 * (1 + tanh(s / delta)) / 2), 0, 255),
+ *   s = z - zc - h(x,y) - eta(x,y,z),  zc = (nz-1)/2,
+ *   delta = 6 / (2 atanh 0.8)   (10% -> 90% over 6 samples),
+ *   h = sum of 32 modes a_m sin(2 pi (p_m x + q_m y) / nx + phi_m), integer
+ *       p, q in [-16,16] not both 0, a_m ~ 1/|(p,q)|, sum a_m = hsum,
+ *   eta = 3-octave value noise (periods 64, 32, 16 samples; amplitudes 16, 8,
+ *       4): smoothstep-weighted trilinear interpolation of hashed lattice
+ *       values in [-1, 1].
+ * |h| <= hsum and |eta| <= 28, so outside the band |s| > 28 + 12 the value is
+ * exactly 0 or 255 and tanh is not evaluated there. */
+
+typedef struct {
+    int nx, ny, nz;
+    double zc, inv_delta, hsum;
+    double *h;            /* nx*ny */
+    float *lat[3];        /* lattice values per octave */
+    int ln[3][3];         /* lattice sizes */
+    int period[3];
+    double amp[3];
+} rm_ctx;
+
+static float lattice_value(uint64_t seed, int oct, int ix, int iy, int iz) {
+    uint64_t s = seed * 0x9e3779b97f4a7c15ULL ^ ((uint64_t)oct << 58) ^ ((uint64_t)(uint32_t)ix << 38) ^
+                 ((uint64_t)(uint32_t)iy << 19) ^ (uint64_t)(uint32_t)iz;
+    return (float)(2.0 * sm64_unit(&s) - 1.0);
+}
+
+static int rm_init(rm_ctx *c, int nx, int ny, int nz, uint64_t seed, double hsum) {
+    memset(c, 0, sizeof(*c));
+    c->nx = nx; c->ny = ny; c->nz = nz;
+    c->zc = 0.5 * (nz - 1);
+    c->inv_delta = (2.0 * atanh(0.8)) / 6.0;
+    c->hsum = hsum;
+    c->h = (double *)malloc(sizeof(double) * (size_t)nx * ny);
+    if (!c->h) return VG_ENOMEM;
+    int pm[32], qm[32];
+    double am[32], ph[32], asum = 0.0;
+    uint64_t s = seed;
+    const double twopi = 6.283185307179586476925286766559;
+    for (int m = 0; m < 32; ++m) {
+        do {
+            pm[m] = (int)(sm64_next(&s) % 33ull) - 16;
+            qm[m] = (int)(sm64_next(&s) % 33ull) - 16;
+        } while (pm[m] == 0 && qm[m] == 0);
+        am[m] = 1.0 / sqrt((double)(pm[m] * pm[m] + qm[m] * qm[m]));
+        asum += am[m];
+        ph[m] = twopi * sm64_unit(&s);
+    }
+    for (int m = 0; m < 32; ++m) am[m] *= hsum / asum;
+    /* separable evaluation: sin(a + b) = sin a cos b + cos a sin b */
+    double *sx = (double *)malloc(sizeof(double) * 32 * (size_t)nx), *cx = (double *)malloc(sizeof(double) * 32 * (size_t)nx);
+    double *sy = (double *)malloc(sizeof(double) * 32 * (size_t)ny), *cy = (double *)malloc(sizeof(double) * 32 * (size_t)ny);
+    if (!sx || !cx || !sy || !cy) { free(sx); free(cx); free(sy); free(cy); return VG_ENOMEM; }
+    for (int m = 0; m < 32; ++m) {
+        for (int x = 0; x < nx; ++x) {
+            double a = twopi * pm[m] * x / (double)nx + ph[m];
+            sx[m * (size_t)nx + x] = sin(a); cx[m * (size_t)nx + x] = cos(a);
+        }
+        for (int y = 0; y < ny; ++y) {
+            double b = twopi * qm[m] * y / (double)nx;
+            sy[m * (size_t)ny + y] = sin(b); cy[m * (size_t)ny + y] = cos(b);
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            double v = 0.0;
+            for (int m = 0; m < 32; ++m)
+                v += am[m] * (sx[m * (size_t)nx + x] * cy[m * (size_t)ny + y] + cx[m * (size_t)nx + x] * sy[m * (size_t)ny + y]);
+            c->h[(size_t)y * nx + x] = v;
+        }
+    free(sx); free(cx); free(sy); free(cy);
+    int periods[3] = {64, 32, 16};
+    double amps[3] = {16.0, 8.0, 4.0};
+    for (int o = 0; o < 3; ++o) {
+        c->period[o] = periods[o];
+        c->amp[o] = amps[o];
+        int lx = nx / periods[o] + 2, ly = ny / periods[o] + 2, lz = nz / periods[o] + 2;
+        c->ln[o][0] = lx; c->ln[o][1] = ly; c->ln[o][2] = lz;
+        c->lat[o] = (float *)malloc(sizeof(float) * (size_t)lx * ly * lz);
+        if (!c->lat[o]) return VG_ENOMEM;
+#pragma omp parallel for schedule(static)
+        for (long iz = 0; iz < lz; ++iz)
+            for (int iy = 0; iy < ly; ++iy)
+                for (int ix = 0; ix < lx; ++ix)
+                    c->lat[o][((size_t)iz * ly + iy) * lx + ix] = lattice_value(seed, o, ix, iy, (int)iz);
+    }
+    return VG_OK;
+}
+
+static void rm_free(rm_ctx *c) {
+    free(c->h);
+    for (int o = 0; o < 3; ++o) free(c->lat[o]);
+}
+
+static inline double smooth01(double t) { return t * t * (3.0 - 2.0 * t); }
+
+static double rm_eta(const rm_ctx *c, int x, int y, int z) {
+    double eta = 0.0;
+    for (int o = 0; o < 3; ++o) {
+        int P = c->period[o];
+        int ix = x / P, iy = y / P, iz = z / P;
+        double fx = smooth01((x - ix * P) / (double)P), fy = smooth01((y - iy * P) / (double)P),
+               fz = smooth01((z - iz * P) / (double)P);
+        const float *L = c->lat[o];
+        int lx = c->ln[o][0], ly = c->ln[o][1];
+#define LV(a, b, d) (double)L[((size_t)(iz + (d)) * ly + (iy + (b))) * lx + (ix + (a))]
+        double v00 = LV(0, 0, 0) + (LV(1, 0, 0) - LV(0, 0, 0)) * fx;
+        double v10 = LV(0, 1, 0) + (LV(1, 1, 0) - LV(0, 1, 0)) * fx;
+        double v01 = LV(0, 0, 1) + (LV(1, 0, 1) - LV(0, 0, 1)) * fx;
+        double v11 = LV(0, 1, 1) + (LV(1, 1, 1) - LV(0, 1, 1)) * fx;
+#undef LV
+        double v0 = v00 + (v10 - v00) * fy, v1 = v01 + (v11 - v01) * fy;
+        eta += c->amp[o] * (v0 + (v1 - v0) * fz);
+    }
+    return eta;
+}
+
+static float rm_value(const rm_ctx *c, int x, int y, int z) {
+    double s0 = z - c->zc - c->h[(size_t)y * c->nx + x];
+    if (s0 > 40.0) return 255.0f;
+    if (s0 < -40.0) return 0.0f;
+    double s = s0 - rm_eta(c, x, y, z);
+    double v = floor(255.0 * 0.5 * (1.0 + tanh(s * c->inv_delta)) + 0.5);
+    if (v < 0) v = 0;
+    if (v > 255) v = 255;
+    return (float)v;
+}
+
+/* Small volumes: the RM-like field itself (tests). */
+int vg_rm_field(int nx, int ny, int nz, uint64_t seed, double hsum, float *out) {
+    if (nx < 2 || ny < 2 || nz < 2 || !out) return VG_EINVAL;
+    rm_ctx c;
+    int rc = rm_init(&c, nx, ny, nz, seed, hsum);
+    if (rc) { rm_free(&c); return rc; }
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) out[((size_t)z * ny + y) * nx + x] = rm_value(&c, x, y, (int)z);
+    rm_free(&c);
+    return VG_OK;
+}
+
+static void build_order(void);
+static void encode_block(const float v[64], int R, uint32_t *rec);
+
+/* Generate and encode the RM-like volume block by block (no full-size
+ * buffer): out holds nblocks * 8 * rate bytes. */
+int vg_rm_encode(int nx, int ny, int nz, uint64_t seed, double hsum, int rate, void *out) {
+    if (nx < 2 || ny < 2 || nz < 2 || !out || !((rate >= 1 && rate <= 16) || rate == 32)) return VG_EINVAL;
+    build_order();
+    rm_ctx c;
+    int rc = rm_init(&c, nx, ny, nz, seed, hsum);
+    if (rc) { rm_free(&c); return rc; }
+    long nbx = (nx + 3) / 4, nby = (ny + 3) / 4, nbz = (nz + 3) / 4;
+    size_t rec_words = 2u * (size_t)rate;
+    /* blocks entirely above / below the band are constant 255 / 0 */
+    uint32_t full_rec[64];
+    {
+        float v255[64];
+        for (int i = 0; i < 64; ++i) v255[i] = 255.0f;
+        encode_block(v255, rate, full_rec);
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long b = 0; b < nbx * nby * nbz; ++b) {
+        long bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+        uint32_t *dst = (uint32_t *)out + (size_t)b * rec_words;
+        double hmin = 1e300, hmax = -1e300;
+        for (int j = 0; j < 4; ++j)
+            for (int i = 0; i < 4; ++i) {
+                long x = 4 * bx + i, y = 4 * by + j;
+                if (x > nx - 1) x = nx - 1;
+                if (y > ny - 1) y = ny - 1;
+                double hv = c.h[(size_t)y * nx + x];
+                if (hv < hmin) hmin = hv;
+                if (hv > hmax) hmax = hv;
+            }
+        long z0 = 4 * bz, z1 = 4 * bz + 3 > nz - 1 ? nz - 1 : 4 * bz + 3;
+        if ((double)z0 - c.zc - hmax > 40.0) { memcpy(dst, full_rec, rec_words * 4); continue; }
+        if ((double)z1 - c.zc - hmin < -40.0) { memset(dst, 0, rec_words * 4); continue; }
+        float v[64];
+        for (int k = 0; k < 4; ++k)
+            for (int j = 0; j < 4; ++j)
+                for (int i = 0; i < 4; ++i) {
+                    long x = 4 * bx + i, y = 4 * by + j, z = 4 * bz + k;
+                    if (x > nx - 1) x = nx - 1;
+                    if (y > ny - 1) y = ny - 1;
+                    if (z > nz - 1) z = nz - 1;
+                    v[i + 4 * j + 16 * k] = rm_value(&c, (int)x, (int)y, (int)z);
+                }
+        encode_block(v, rate, dst);
+    }
+    rm_free(&c);
+    return VG_OK;
+}
+
 /* ----------------------------------------------------- order statistic --- */
 
 static inline uint32_t f2key(float f) {
@@ -331,27 +529,37 @@ static void encode_block(const float v[64], int R, uint32_t *rec) {
     bitwriter bw = {rec, 0, 64u * (uint32_t)R};
     put_bit(&bw, 1);
     for (int i = 0; i < 8; ++i) put_bit(&bw, ((uint32_t)(e + 127) >> i) & 1u);
-    uint8_t sig[64] = {0};
+    /* plane masks: bit j of pm[k] = bit k of mag[j] (order space) */
+    uint64_t pm[30] = {0};
+    for (int j = 0; j < 64; ++j)
+        for (int k = 0; k < 30; ++k)
+            if ((mag[j] >> k) & 1u) pm[k] |= 1ull << j;
+    uint64_t negm = 0;
+    for (int j = 0; j < 64; ++j) negm |= (uint64_t)neg[j] << j;
+    uint64_t sig = 0;
     for (int k = 29; k >= 0; --k) {
-        for (int j = 0; j < 64; ++j)
-            if (sig[j] && !put_bit(&bw, (mag[j] >> k) & 1u)) return;
+        uint64_t m = sig;
+        while (m) {
+            int j = __builtin_ctzll(m);
+            m &= m - 1;
+            if (!put_bit(&bw, (uint32_t)((pm[k] >> j) & 1u))) return;
+        }
         int c = 0;
         for (;;) {
-            int any_cand = 0, any_bit = 0;
-            for (int j = c; j < 64; ++j)
-                if (!sig[j]) { any_cand = 1; if ((mag[j] >> k) & 1u) any_bit = 1; }
-            if (!any_cand) break;
-            if (!put_bit(&bw, (uint32_t)any_bit)) return;
-            if (!any_bit) break;
-            int target = -1;
-            for (int j = c; j < 64; ++j) {
-                if (sig[j]) continue;
-                uint32_t b = (mag[j] >> k) & 1u;
-                if (!put_bit(&bw, b)) return;
-                if (b) { target = j; break; }
-            }
-            if (!put_bit(&bw, neg[target])) return;
-            sig[target] = 1;
+            uint64_t cand = c >= 64 ? 0ull : (~sig & (~0ull << c));
+            if (!cand) break;
+            uint32_t any = (pm[k] & cand) != 0;
+            if (!put_bit(&bw, any)) return;
+            if (!any) break;
+            int target = __builtin_ctzll(pm[k] & cand);
+            /* one zero bit per candidate before the target, then its 1 */
+            uint64_t before = cand & ((1ull << target) - 1ull);
+            int nz = __builtin_popcountll(before);
+            for (int z = 0; z < nz; ++z)
+                if (!put_bit(&bw, 0)) return;
+            if (!put_bit(&bw, 1)) return;
+            if (!put_bit(&bw, (uint32_t)((negm >> target) & 1u))) return;
+            sig |= 1ull << target;
             c = target + 1;
         }
     }
