@@ -94,7 +94,7 @@ struct spr_render {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t graph_gen = ~0ull;
-    uint64_t fwords = 0, cwords = 0;   // isovalue mask sizes (u32 words)
+    uint64_t cwords = 0;   // isovalue mask size (one u64 per coarse cell)
 };
 
 struct spr_batch {
@@ -201,7 +201,7 @@ PassGrids grids_for(const spr_ctx *c, uint64_t max_A, uint64_t max_P) {
     pg.slots = g(c->cache.n_slots, 256, 2048);
     pg.assign = 256;
     pg.scatter = g(max_P, 256, 2048);
-    pg.decode = g(8 * max_P, 64, 4096);
+    pg.decode = g(8 * max_P, 64, 1024);
     return pg;
 }
 
@@ -640,8 +640,7 @@ static void free_render_buffers(spr_ctx *c, spr_render *r) {
     dfree(c, q.hits, n);
     dfree(c, r->d_st, 1);
     dfree(c, r->d_req, 1);
-    dfree(c, q.fmask, r->fwords);
-    dfree(c, q.cmask, r->cwords);
+    dfree(c, q.cmask64, r->cwords);
     free_table(c, r->table);
 }
 
@@ -682,11 +681,9 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
         if ((st = dalloc(c, 1, &r->d_req)) != SPR_OK) break;
         {
             const VolDev &V = c->h_vols[v->idx];
-            r->fwords = (V.nblocks + 31) / 32;
-            r->cwords = ((uint64_t)V.nc[0] * V.nc[1] * V.nc[2] + 31) / 32;
+            r->cwords = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
         }
-        if ((st = dalloc(c, r->fwords, &q.fmask)) != SPR_OK) break;
-        if ((st = dalloc(c, r->cwords, &q.cmask)) != SPR_OK) break;
+        if ((st = dalloc(c, r->cwords, &q.cmask64)) != SPR_OK) break;
         if ((st = alloc_table(c, 1, round64h(npix), npix, r->table)) != SPR_OK) break;
         st = ensure_work(c, npix);
     } while (0);
@@ -705,7 +702,7 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     hipError_t e = hipMemcpy(r->d_st, &s0, sizeof(s0), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r->table.hdr, &one, sizeof(one), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r->d_req, &q, sizeof(q), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols, r->fwords + r->cwords);
+    if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols, r->cwords);
     if (e != hipSuccess) {
         free_render_buffers(c, r);
         delete r;

@@ -81,8 +81,8 @@ struct ReqDev {
     uint32_t *image;            // RGBA8 per pixel
     spr_hit *hits;              // per pixel
     ReqState *st;
-    uint32_t *fmask;            // per block: fine range contains iso (1 bit, by block id)
-    uint32_t *cmask;            // per coarse cell: coarse range contains iso
+    uint64_t *cmask64;          // per coarse cell: bit (bx&3) + 4(by&3) + 16(bz&3) set when that
+                                // block's fine range contains iso (0 when the coarse range does not)
 };
 
 // Per-pass control block of a context (counters reset at each pass start).

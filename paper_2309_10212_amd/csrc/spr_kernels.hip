@@ -71,6 +71,18 @@ __device__ __forceinline__ void inv4(int32_t &p0, int32_t &p1, int32_t &p2, int3
 // Decodes the record into q[64] (raster order) and the block exponent.
 // Returns false for an all-zero block (q untouched).  s_mag: this wave's
 // 64x64 u32 LDS area; lane: lane id within the wave.
+//
+// The decoder is one flat loop in which every active lane consumes exactly
+// one bit per iteration; the meaning of the bit depends on the lane's mode:
+//   REF   refinement bit of the next significant coefficient (mask R),
+//   GT    group test over the candidates from the cursor (mask C),
+//   SCAN  next candidate's plane bit (mask I), the first 1 is the target,
+//   SIGN  the target's sign; it becomes significant.
+// Transitions that consume no bit (end of refinement, no candidate left, next
+// plane) are settled after each bit.  Lanes decoding different blocks stay in
+// lockstep: a wave takes about as many iterations as one block has bits.
+enum : uint32_t { M_REF = 0, M_GT = 1, M_SCAN = 2, M_SIGN = 3, M_DONE = 4 };
+
 template <int RWMAX>
 __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, int rate, uint32_t *s_mag,
                                               uint32_t lane, int32_t (&q)[64], int &e_out) {
@@ -83,62 +95,51 @@ __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, 
     const uint32_t B = 64u * (uint32_t)rate;
     uint64_t buf = ((uint64_t)w[0] | ((uint64_t)w[1] << 32)) >> 9;
     uint32_t nbits = 55, wi = 2, pos = 9;
-    uint64_t S = 0, NEG = 0;
-#define SPR_READBIT(dst)                                            \
-    do {                                                            \
-        dst = (uint32_t)(buf & 1ull);                               \
-        buf >>= 1;                                                  \
-        --nbits;                                                    \
-        ++pos;                                                      \
-        if (nbits < 32) {                                           \
-            buf |= (uint64_t)pick_word<RWMAX>(w, wi) << nbits;      \
-            nbits += 32;                                            \
-            ++wi;                                                   \
-        }                                                           \
-    } while (0)
-    for (int k = 29; k >= 0; --k) {
-        // refinement: one bit per coefficient significant before this plane
-        uint64_t m = S;
-        while (m) {
-            if (pos >= B) goto done;
-            uint32_t b;
-            SPR_READBIT(b);
-            uint32_t j = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-            m &= m - 1ull;
-            if (b) s_mag[j * 64 + lane] |= 1u << k;
+    uint64_t S = 0, NEG = 0, R = 0, C = ~0ull, I = 0;
+    int k = 29;
+    uint32_t mode = M_GT, t = 0;   // plane 29 has nothing to refine
+    for (;;) {
+        if (mode == M_DONE || pos >= B) break;
+        const uint32_t bit = (uint32_t)(buf & 1ull);
+        buf >>= 1;
+        --nbits;
+        ++pos;
+        if (nbits < 32) {
+            buf |= (uint64_t)pick_word<RWMAX>(w, wi) << nbits;
+            nbits += 32;
+            ++wi;
         }
-        // significance: group tests over the insignificant ones from cursor c
-        {
-            uint32_t c = 0;
-            for (;;) {
-                uint64_t I = c >= 64 ? 0ull : (~S & (~0ull << c));
-                if (I == 0) break;
-                if (pos >= B) goto done;
-                uint32_t g;
-                SPR_READBIT(g);
-                if (!g) break;
-                int t = -1;
-                while (I) {
-                    if (pos >= B) goto done;
-                    uint32_t b;
-                    SPR_READBIT(b);
-                    int j = __ffsll((unsigned long long)I) - 1;
-                    I &= I - 1ull;
-                    if (b) { t = j; break; }
-                }
-                if (t < 0) goto done;
-                if (pos >= B) goto done;
-                uint32_t sg;
-                SPR_READBIT(sg);
-                NEG |= (uint64_t)sg << t;
-                s_mag[(uint32_t)t * 64 + lane] = 1u << k;
-                S |= 1ull << t;
-                c = (uint32_t)t + 1;
-            }
+        bool next_plane = false;
+        if (mode == M_REF) {
+            uint32_t j = (uint32_t)__ffsll((unsigned long long)R) - 1u;
+            R &= R - 1ull;
+            if (bit) s_mag[j * 64 + lane] |= 1u << k;
+            if (R == 0) { mode = M_GT; C = ~S; }
+        } else if (mode == M_GT) {
+            if (bit) { mode = M_SCAN; I = C; }
+            else next_plane = true;
+        } else if (mode == M_SCAN) {
+            uint32_t j = (uint32_t)__ffsll((unsigned long long)I) - 1u;
+            I &= I - 1ull;
+            if (bit) { mode = M_SIGN; t = j; }
+            else if (I == 0) mode = M_DONE;   // no candidate had the bit: not a valid record
+        } else {   // M_SIGN
+            NEG |= (uint64_t)bit << t;
+            s_mag[t * 64 + lane] = 1u << k;
+            S |= 1ull << t;
+            mode = M_GT;
+            C = t >= 63 ? 0ull : (~S & (~0ull << (t + 1)));
+        }
+        // settle the transitions that read no bit
+        for (int guard = 0; guard < 4; ++guard) {
+            if (mode == M_GT && C == 0) next_plane = true;
+            if (!next_plane) break;
+            next_plane = false;
+            if (--k < 0) { mode = M_DONE; break; }
+            if (S) { mode = M_REF; R = S; }
+            else { mode = M_GT; C = ~0ull; }
         }
     }
-done:
-#undef SPR_READBIT
 #pragma unroll
     for (int j = 0; j < 64; ++j) {
         int32_t v = 0;   // magnitudes are below 2^30
@@ -391,37 +392,38 @@ __global__ void k_pass_begin(PassCtl *ctl, Table T, int is_init) {
 }
 
 // ----------------------------------------------------------- isovalue masks --
-// Per request, one bit per block (fine grid) and per coarse cell: the range
-// contains the isovalue (inclusive, compared in float32, exactly the test the
-// traversal needs).  256 KB for 2M blocks: the traversal's per-step test then
-// hits L2 instead of the 8-byte ranges.
+// Per request and coarse cell, one 64-bit word: bit (bx&3) + 4(by&3) +
+// 16(bz&3) is set when that block's fine range contains the isovalue
+// (inclusive, compared in float32: exactly the test the traversal needs).
+// The word is 0 when the coarse range does not contain the isovalue (Sec. 3.1
+// coarse grid), and a zero word lets the traversal skip the whole coarse cell.
+// The walk loads one word per coarse cell and tests blocks in registers.
 __global__ void k_iso_masks(Table T, const VolDev *vols) {
     const ReqDev &q = T.reqs[0];
     const VolDev &V = vols[q.vol];
     const float iso = q.iso;
-    const uint64_t nfw = (V.nblocks + 31) / 32;
     const uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
-    const uint64_t ncw = (nc + 31) / 32;
-    for (uint64_t wdx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; wdx < nfw + ncw;
-         wdx += (uint64_t)gridDim.x * blockDim.x) {
-        bool coarse = wdx >= nfw;
-        uint64_t w0 = (coarse ? wdx - nfw : wdx) * 32;
-        uint64_t lim = coarse ? nc : V.nblocks;
-        const float2 *rng = coarse ? V.coarse : V.fine;
-        uint32_t bits = 0;
-        for (int i = 0; i < 32; ++i) {
-            uint64_t id = w0 + i;
-            if (id < lim) {
-                float2 r = rng[id];
-                bits |= (uint32_t)(r.x <= iso && iso <= r.y) << i;
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nc; c += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t bits = 0;
+        float2 cr = V.coarse[c];
+        if (cr.x <= iso && iso <= cr.y) {
+            int cx = (int)(c % (uint64_t)V.nc[0]);
+            int cy = (int)((c / (uint64_t)V.nc[0]) % (uint64_t)V.nc[1]);
+            int cz = (int)(c / ((uint64_t)V.nc[0] * V.nc[1]));
+            for (int i = 0; i < 64; ++i) {
+                int x = 4 * cx + (i & 3), y = 4 * cy + ((i >> 2) & 3), z = 4 * cz + (i >> 4);
+                if (x >= V.nb[0] || y >= V.nb[1] || z >= V.nb[2]) continue;
+                float2 r = V.fine[((uint64_t)z * V.nb[1] + y) * V.nb[0] + x];
+                bits |= (uint64_t)(r.x <= iso && iso <= r.y) << i;
             }
         }
-        if (coarse) q.cmask[wdx - nfw] = bits;
-        else q.fmask[wdx] = bits;
+        q.cmask64[c] = bits;
     }
 }
 
-__device__ __forceinline__ bool mask_bit(const uint32_t *m, uint64_t id) { return (m[id >> 5] >> (id & 31)) & 1u; }
+__device__ __forceinline__ uint32_t local_bit(const int cb[3]) {
+    return (uint32_t)((cb[0] & 3) + 4 * (cb[1] & 3) + 16 * (cb[2] & 3));
+}
 
 // ------------------------------------------------------------ initial rays --
 // Sec. 3.2: one thread per pixel computes the ray and its volume entry; rays
@@ -506,19 +508,19 @@ __global__ __launch_bounds__(256, 5) void k_traverse(PassCtl *ctl, Table T, cons
             if (tn > R.tx || !advance(R, LB, cb, tn, zero3, tbhi)) alive = false;
             tcur = tn;
             bvalid = true;
-            ctest = (cb[0] >> 2) != cc[0] || (cb[1] >> 2) != cc[1] || (cb[2] >> 2) != cc[2];
-            if (ctest) {
+            ctest = true;   // (re)load the coarse cell's block bits
 #pragma unroll
-                for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
-            }
+            for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
         }
+        uint64_t cm = 0;
         const int max_steps = V.tb[0] + V.tb[1] + V.tb[2] + V.tc[0] + V.tc[1] + V.tc[2] + 8;
         int steps = 0;
         while (alive && found < ns) {
             if (++steps > max_steps) { alive = false; break; }   // every step advances an index
             if (ctest) {
                 const uint64_t cid = ((uint64_t)cc[2] * V.nc[1] + cc[1]) * V.nc[0] + cc[0];
-                if (mask_bit(q.cmask, cid)) {
+                cm = q.cmask64[cid];
+                if (cm != 0) {
                     if (!bvalid) {
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
@@ -537,9 +539,9 @@ __global__ __launch_bounds__(256, 5) void k_traverse(PassCtl *ctl, Table T, cons
                     continue;
                 }
             }
-            const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * V.nb[1] + cb[1]) * V.nb[0] + cb[0]);
-            const bool emit = mask_bit(q.fmask, bid);
+            const bool emit = (cm >> local_bit(cb)) & 1ull;
             if (emit) {
+                const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * V.nb[1] + cb[1]) * V.nb[0] + cb[0]);
                 slots[found] = bid;
                 found++;
                 if (found == ns) break;
@@ -988,6 +990,7 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
 __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const VolDev *vols) {
     const uint32_t A = ctl->A;
     const uint32_t vadm = admitted_blocks(ctl);
+    const bool all_served = vadm == ctl->n_vis;   // no deferral this pass: skip the per-slot check
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
         // all lanes of a wave share a request (the A space is 64-aligned per request)
         uint32_t r = __builtin_amdgcn_readfirstlane(find_req(T.act_base, ctl->nreq, p));
@@ -1011,11 +1014,12 @@ __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const 
                     break;
                 }
                 my_pairs++;
+                const bool served = all_served || V.vis_idx[b] < vadm;
                 if (stopped || term) {
-                    if (V.vis_idx[b] >= vadm) my_def++;
+                    if (!served) my_def++;
                     continue;
                 }
-                if (V.vis_idx[b] >= vadm) {
+                if (!served) {
                     stopped = true;
                     my_def++;
                     continue;
