@@ -197,6 +197,7 @@ PassGrids grids_for(const spr_ctx *c, uint64_t max_A, uint64_t max_P) {
     PassGrids pg;
     pg.rays = g(max_A, 256, 2048);
     pg.pairs = g(max_P, 256, 2048);
+    pg.dedupe = g(max_P, 1024, 2048);
     pg.blocks = g(8 * max_P, 256, 2048);
     pg.slots = g(c->cache.n_slots, 256, 2048);
     pg.assign = 256;
@@ -211,12 +212,12 @@ spr_status ensure_work(spr_ctx *c, uint64_t P) {
     HIPCHK(hipStreamSynchronize(c->stream));
     Work &W = c->work;
     size_t oP = W.cap_P, oK = W.cap_K;
-    dfree(c, W.vis_list, oP); dfree(c, W.vis_cnt, oP); dfree(c, W.vis_off, oP);
+    dfree(c, W.vis_list, oP); dfree(c, W.vis_off, oP);
     dfree(c, W.act_list, oK); dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
     dfree(c, W.pair_rank, oP); dfree(c, W.s_ray, oP); dfree(c, W.s_q, oP); dfree(c, W.s_vi, oP);
     W.cap_P = 0; W.cap_K = 0;
     uint64_t cP = P, cK = 8 * P;
-    CHK(dalloc(c, cP, &W.vis_list)); CHK(dalloc(c, cP, &W.vis_cnt)); CHK(dalloc(c, cP, &W.vis_off));
+    CHK(dalloc(c, cP, &W.vis_list)); CHK(dalloc(c, cP, &W.vis_off));
     CHK(dalloc(c, cK, &W.act_list)); CHK(dalloc(c, cK, &W.miss_list)); CHK(dalloc(c, cK, &W.miss_slot));
     CHK(dalloc(c, cP, &W.pair_rank)); CHK(dalloc(c, cP, &W.s_ray)); CHK(dalloc(c, cP, &W.s_q));
     CHK(dalloc(c, cP, &W.s_vi));
@@ -233,7 +234,7 @@ spr_status alloc_table(spr_ctx *c, uint32_t cap, uint64_t max_A, uint64_t max_P,
     CHK(dalloc(c, 1, &T.hdr));
     CHK(dalloc(c, cap + 1, &T.act_base));
     CHK(dalloc(c, cap + 1, &T.pair_base));
-    CHK(dalloc(c, max_A / 64 + 2, &T.wave_cnt));
+    CHK(dalloc(c, max_A / 64 + 2, &T.wave_rec));
     CHK(dalloc(c, max_A / 64 + 2, &T.wave_off));
     return SPR_OK;
 }
@@ -242,7 +243,7 @@ void free_table(spr_ctx *c, Table &T) {
     dfree(c, T.hdr, 1);
     dfree(c, T.act_base, T.cap + 1);
     dfree(c, T.pair_base, T.cap + 1);
-    dfree(c, T.wave_cnt, T.max_A / 64 + 2);
+    dfree(c, T.wave_rec, T.max_A / 64 + 2);
     dfree(c, T.wave_off, T.max_A / 64 + 2);
 }
 
@@ -383,7 +384,7 @@ spr_status spr_ctx_destroy(spr_ctx *c) {
     if (c->stream || true) (void)hipStreamSynchronize(c->stream);
     Work &W = c->work;
     size_t oP = W.cap_P, oK = W.cap_K;
-    dfree(c, W.vis_list, oP); dfree(c, W.vis_cnt, oP); dfree(c, W.vis_off, oP);
+    dfree(c, W.vis_list, oP); dfree(c, W.vis_off, oP);
     dfree(c, W.act_list, oK); dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
     dfree(c, W.pair_rank, oP); dfree(c, W.s_ray, oP); dfree(c, W.s_q, oP); dfree(c, W.s_vi, oP);
     size_t ns = c->cache.n_slots;
@@ -462,7 +463,7 @@ static void free_volume_buffers(spr_ctx *c, VolDev &V, size_t stream_bytes) {
     dfree(c, V.fine, nb);
     dfree(c, V.coarse, nc);
     dfree(c, V.map, nb);
-    dfree(c, V.vis_stamp, nb);
+    dfree(c, V.blk_cnt, nb);
     dfree(c, V.vis_idx, nb);
     dfree(c, V.act_stamp, nb);
     dfree(c, V.blk, nb);
@@ -509,7 +510,7 @@ spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, co
         if ((st = dalloc(c, nb, &V.fine)) != SPR_OK) break;
         if ((st = dalloc(c, nc, &V.coarse)) != SPR_OK) break;
         if ((st = dalloc(c, nb, &V.map)) != SPR_OK) break;
-        if ((st = dalloc(c, nb, &V.vis_stamp)) != SPR_OK) break;
+        if ((st = dalloc(c, nb, &V.blk_cnt)) != SPR_OK) break;
         if ((st = dalloc(c, nb, &V.vis_idx)) != SPR_OK) break;
         if ((st = dalloc(c, nb, &V.act_stamp)) != SPR_OK) break;
         if ((st = dalloc(c, nb, &V.blk)) != SPR_OK) break;
@@ -520,7 +521,7 @@ spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, co
     }
     hipError_t e = hipMemcpyAsync(sp, host_stream, bytes, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_fill_u32(c->stream, V.map, nb, NONE);
-    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.vis_stamp, nb, 0);
+    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.blk_cnt, nb, 0);
     if (e == hipSuccess) e = launch_fill_u32(c->stream, V.vis_idx, nb, 0);
     if (e == hipSuccess) e = launch_fill_u32(c->stream, V.act_stamp, nb, 0);
     if (e == hipSuccess) e = launch_load_grids(c->stream, V);

@@ -30,7 +30,7 @@ struct VolDev {
     float2 *fine;               // per block: union of the 2x2x2 block neighbourhood
     float2 *coarse;             // per 4^3 blocks: union of fine ranges
     uint32_t *map;              // per block: cache slot or NONE
-    uint32_t *vis_stamp;        // per block: last pass it was visible
+    uint32_t *blk_cnt;          // per block: pairs on it in the current pass (0 between passes)
     uint32_t *vis_idx;          // per block: index in that pass's visible list
     uint32_t *act_stamp;        // per block: last pass it was active
     int n[3];                   // samples per axis
@@ -125,8 +125,9 @@ struct Table {
                                 // so membership can change between graph replays)
     uint32_t *act_base;         // cap+1, 64-aligned prefix of n_act
     uint32_t *pair_base;        // cap+1, prefix of n_act*n_spec
-    uint32_t *wave_cnt;         // survivors per 64-entry wave of the A space
-    uint32_t *wave_off;
+    uint4 *wave_rec;            // per 64-entry wave of the A space: survivors, pairs,
+                                // deferred pairs, terminated rays
+    uint32_t *wave_off;         // exclusive prefix of the survivors
     uint32_t cap;               // request capacity
     uint32_t max_A;             // capacity of the A space (sum of padded npix)
     uint32_t max_P;             // capacity of the pair space (sum of npix)
@@ -135,7 +136,6 @@ struct Table {
 // Context-level scratch for one pass, sized for the largest table.
 struct Work {
     uint64_t *vis_list;         // (vol << 32) | block
-    uint32_t *vis_cnt;          // pairs per visible block
     uint32_t *vis_off;          // start of the block's run in the sorted pairs
     uint64_t *act_list;         // active blocks (vol << 32) | block
     uint64_t *miss_list;        // misses (vol << 32) | block
@@ -163,6 +163,41 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() {
     uint32_t l = lane_id();
     return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Block-aggregated bump allocation.  Every thread of the workgroup calls it
+// (block-uniform control flow) with a count and receives the start of its run
+// of `cnt` entries; the workgroup issues a single atomic on *counter.  Device
+// atomics on one address serialise (about 12 ns each on this chip, measured),
+// so appends aggregate per workgroup, not per wave.  s_tmp: BS/64 + 1 words.
+template <int BS>
+__device__ __forceinline__ uint32_t block_bump(uint32_t *counter, uint32_t cnt, uint32_t *s_tmp) {
+    static_assert(BS % 64 == 0 && BS <= 4096, "block_bump: workgroup of whole waves, at most 64 of them");
+    constexpr uint32_t NW = BS / 64;
+    const uint32_t l = lane_id(), w = threadIdx.x >> 6;
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(incl, off);
+        if ((int)l >= off) incl += o;
+    }
+    if (l == 63) s_tmp[w] = incl;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t v = l < NW ? s_tmp[l] : 0u;
+        uint32_t x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            uint32_t o = __shfl_up(x, off);
+            if ((int)l >= off) x += o;
+        }
+        if (l < NW) s_tmp[l] = x - v;
+        if (l == 63) s_tmp[NW] = x ? atomicAdd(counter, x) : 0u;
+    }
+    __syncthreads();
+    const uint32_t r = s_tmp[NW] + s_tmp[w] + incl - cnt;
+    __syncthreads();   // s_tmp may be reused right away
+    return r;
 }
 
 // Wave-aggregated append: every active lane calls it; lanes with want get

@@ -451,7 +451,7 @@ __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
             q.act[1][i] = i;
         }
         uint64_t m = __ballot(alive);
-        if (lane_id() == 0) T.wave_cnt[p >> 6] = (uint32_t)__popcll(m);
+        if (lane_id() == 0) T.wave_rec[p >> 6] = make_uint4((uint32_t)__popcll(m), 0u, 0u, 0u);
     }
 }
 
@@ -556,45 +556,80 @@ __global__ __launch_bounds__(256, 5) void k_traverse(PassCtl *ctl, Table T, cons
             }
         }
         for (uint32_t k = found; k < ns; ++k) slots[k] = NONE;
+        // The block of pair 0 (the first active ray's first candidate) takes
+        // visible-list index 0, so it is always admitted and every pass makes
+        // progress under the cache-capacity rule: reserve that index.
+        if (found > 0 && T.pair_base[r] + i * ns == 0) ctl->n_vis = 1u;
     }
 }
 
 // --------------------------------------------------------------- K1b ------
-// Visible blocks (Sec. 3.4): one thread per pair slot; the first visitor of a
-// block in this pass (per-block pass stamp) appends it to the visible list
-// and records its index; its pair count starts at 0.
+// Visible blocks (Sec. 3.4) and pair ranks (the N_BRays count of Sec. 3.6) in
+// one atomic per pair: the pair takes its rank within its block from the
+// block's pass counter; rank 0 is the first visitor, which appends the block
+// to the visible list and records its index (pair 0's block takes the
+// reserved index 0).  Counters are zero between
+// passes (K2 clears the ones it reads).  Each thread takes DD_ITEMS pairs, so
+// a workgroup appends DD_ITEMS*256 pairs' worth of blocks with one atomic.
+constexpr int DD_ITEMS = 4;
+
 __global__ __launch_bounds__(256) void k_dedupe(PassCtl *ctl, Table T, const VolDev *vols, Work W) {
+    __shared__ uint32_t s_tmp[256 / 64 + 1];
     const uint32_t P = ctl->P;
-    const uint32_t pass = ctl->pass;
-    for (uint32_t x0 = blockIdx.x * blockDim.x; x0 < P; x0 += gridDim.x * blockDim.x) {
-        const uint32_t x = x0 + threadIdx.x;
-        bool first = false;
-        uint32_t b = NONE, vol = 0;
-        if (x < P) {
-            uint32_t r = find_req(T.pair_base, ctl->nreq, x);
-            const ReqDev &q = T.reqs[r];
-            b = q.pair_blk[x - T.pair_base[r]];
-            vol = q.vol;
-            if (b != NONE) {
-                uint32_t *stp = &vols[vol].vis_stamp[b];
-                if (__hip_atomic_load(stp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pass)
-                    first = atomicExch(stp, pass) != pass;
+    const uint32_t nreq = ctl->nreq;
+    if (P == 0) return;
+    // pair 0's block owns the reserved index 0 (set up by the traversal)
+    const uint32_t r0 = find_req(T.pair_base, nreq, 0u);
+    const uint32_t b0 = T.reqs[r0].pair_blk[0];
+    const uint32_t vol0 = T.reqs[r0].vol;
+    constexpr uint32_t SPAN = 256u * DD_ITEMS;
+    for (uint32_t x0 = blockIdx.x * SPAN; x0 < P; x0 += gridDim.x * SPAN) {
+        uint32_t b[DD_ITEMS], vol[DD_ITEMS];
+        uint32_t firsts = 0, nf = 0;
+#pragma unroll
+        for (int k = 0; k < DD_ITEMS; ++k) {
+            const uint32_t x = x0 + (uint32_t)k * 256u + threadIdx.x;
+            b[k] = NONE;
+            vol[k] = 0;
+            if (x < P) {
+                const uint32_t r = find_req(T.pair_base, nreq, x);
+                const ReqDev &q = T.reqs[r];
+                b[k] = q.pair_blk[x - T.pair_base[r]];
+                vol[k] = q.vol;
+                if (b[k] != NONE) {
+                    const uint32_t rank = atomicAdd(&vols[vol[k]].blk_cnt[b[k]], 1u);
+                    W.pair_rank[x] = rank;
+                    if (rank == 0) {
+                        if (b[k] == b0 && vol[k] == vol0) {
+                            W.vis_list[0] = ((uint64_t)vol0 << 32) | b0;
+                            vols[vol0].vis_idx[b0] = 0u;
+                        } else {
+                            firsts |= 1u << k;
+                            nf++;
+                        }
+                    }
+                }
             }
         }
-        uint32_t idx = wave_append(&ctl->n_vis, first);
-        if (first) {
-            W.vis_list[idx] = ((uint64_t)vol << 32) | b;
-            vols[vol].vis_idx[b] = idx;
-            W.vis_cnt[idx] = 0;
+        uint32_t idx = block_bump<256>(&ctl->n_vis, nf, s_tmp);
+#pragma unroll
+        for (int k = 0; k < DD_ITEMS; ++k) {
+            if ((firsts >> k) & 1u) {
+                W.vis_list[idx] = ((uint64_t)vol[k] << 32) | b[k];
+                vols[vol[k]].vis_idx[b[k]] = idx;
+                idx++;
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------- K2 ------
-// Role A (per pair): rank of the pair within its visible block (atomic count,
-// the N_BRays of Sec. 3.6) and served/deferred accounting.  Role B (per
-// admitted visible block): mark the block and its +x/+y/+z face, edge and
-// corner neighbours active (Sec. 3.4), first visitors append to the active list.
+// Per visible block: read and clear its pair count.  An admitted block
+// (Sec. 3.4 cache-capacity rule) gets its run of sorted pairs (O_BRays of
+// Sec. 3.6) by block-aggregated bump allocation, and marks itself and its
+// +x/+y/+z face, edge and corner neighbours active (Sec. 3.4); first visitors
+// (per-block pass stamp) append to the active list.  Pairs on blocks beyond
+// the admitted prefix are counted as deferred.
 
 __device__ __forceinline__ uint32_t admitted_blocks(const PassCtl *ctl) {
     uint32_t nv = ctl->n_vis;
@@ -602,88 +637,85 @@ __device__ __forceinline__ uint32_t admitted_blocks(const PassCtl *ctl) {
     return nv < cap ? nv : cap;
 }
 
-__global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, Table T, const VolDev *vols, Work W) {
-    const uint32_t P = ctl->P;
+__global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, Work W) {
+    __shared__ uint32_t s_tmp[256 / 64 + 1];
+    __shared__ uint32_t s_def;
+    const uint32_t nv = ctl->n_vis;
     const uint32_t vadm = admitted_blocks(ctl);
     const uint32_t pass = ctl->pass;
-    const uint32_t total = P + vadm;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    uint32_t n_served = 0, n_def = 0;
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += stride) {
-        if (x < P) {
-            uint32_t r = find_req(T.pair_base, ctl->nreq, x);
-            const ReqDev &q = T.reqs[r];
-            uint32_t b = q.pair_blk[x - T.pair_base[r]];
-            if (b != NONE) {
-                uint32_t vi = vols[q.vol].vis_idx[b];
-                W.pair_rank[x] = atomicAdd(&W.vis_cnt[vi], 1u);
-                if (vi < vadm) n_served++;
-                else n_def++;
-            }
-        } else {
-            uint32_t j = x - P;
-            uint64_t e = W.vis_list[j];
+    if (threadIdx.x == 0) s_def = 0;
+    uint32_t my_def = 0;
+    for (uint32_t x0 = blockIdx.x * 256u; x0 < nv; x0 += gridDim.x * 256u) {
+        const uint32_t j = x0 + threadIdx.x;
+        uint32_t cnt = 0, newmask = 0, nnew = 0;
+        uint64_t e = 0;
+        int bx = 0, by = 0, bz = 0;
+        if (j < nv) {
+            e = W.vis_list[j];
             const VolDev &V = vols[(uint32_t)(e >> 32)];
-            uint32_t b = (uint32_t)e;
-            int bx = (int)(b % (uint32_t)V.nb[0]);
-            int by = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
-            int bz = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
-            for (int o = 0; o < 8; ++o) {
-                int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
-                bool ok = x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2];
-                bool first = false;
-                uint32_t nbid = 0;
-                if (ok) {
-                    nbid = (uint32_t)(((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2);
-                    if (__hip_atomic_load(&V.act_stamp[nbid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pass)
-                        first = atomicExch(&V.act_stamp[nbid], pass) != pass;
+            const uint32_t b = (uint32_t)e;
+            cnt = V.blk_cnt[b];
+            V.blk_cnt[b] = 0u;
+            if (j < vadm) {
+                bx = (int)(b % (uint32_t)V.nb[0]);
+                by = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
+                bz = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    const int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
+                    if (x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2]) {
+                        const uint32_t nbid = (uint32_t)(((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2);
+                        uint32_t *stp = &V.act_stamp[nbid];
+                        if (__hip_atomic_load(stp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pass &&
+                            atomicExch(stp, pass) != pass) {
+                            newmask |= 1u << o;
+                            nnew++;
+                        }
+                    }
                 }
-                uint32_t idx = wave_append(&ctl->n_actblk, first);
-                if (first) W.act_list[idx] = (e & 0xFFFFFFFF00000000ull) | nbid;
+            } else {
+                my_def += cnt;
+            }
+        }
+        const uint32_t off = block_bump<256>(&ctl->cursor, j < vadm ? cnt : 0u, s_tmp);
+        if (j < vadm) W.vis_off[j] = off;
+        uint32_t a = block_bump<256>(&ctl->n_actblk, nnew, s_tmp);
+        if (newmask) {
+            const VolDev &V = vols[(uint32_t)(e >> 32)];
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                if ((newmask >> o) & 1u) {
+                    const int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
+                    const uint32_t nbid = (uint32_t)(((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2);
+                    W.act_list[a++] = (e & 0xFFFFFFFF00000000ull) | nbid;
+                }
             }
         }
     }
-    // block-level reduction of the counters
-    __shared__ uint32_t s_cnt[2];
-    if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
+    if (my_def) atomicAdd(&s_def, my_def);
     __syncthreads();
-    if (n_served) atomicAdd(&s_cnt[0], n_served);
-    if (n_def) atomicAdd(&s_cnt[1], n_def);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (s_cnt[0]) atomicAdd(&ctl->served, s_cnt[0]);
-        if (s_cnt[1]) atomicAdd(&ctl->deferred, s_cnt[1]);
-    }
+    if (threadIdx.x == 0 && s_def) atomicAdd(&ctl->deferred, s_def);
 }
 
 // ---------------------------------------------------------------- K3 ------
-// Role A (per active block): cache lookup; a hit refreshes the slot's LRU
-// stamp, a miss is appended to the miss list (Sec. 3.5).  Role B (per
-// admitted visible block): allocate the block's run of sorted pairs
-// (O_BRays of Sec. 3.6) by wave-aggregated bump allocation.
+// Per active block: cache lookup; a hit refreshes the slot's LRU stamp, a miss
+// is appended to the miss list (Sec. 3.5).
 __global__ __launch_bounds__(256) void k_lookup(PassCtl *ctl, const VolDev *vols, Work W, Cache C) {
+    __shared__ uint32_t s_tmp[256 / 64 + 1];
     const uint32_t K = ctl->n_actblk;
-    const uint32_t vadm = admitted_blocks(ctl);
     const uint32_t pass = ctl->pass;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    // role B first so that whole waves stay together for the wave scan
-    const uint32_t nB = round64(vadm);
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nB + K; x += stride) {
-        if (x < nB) {
-            uint32_t cnt = x < vadm ? W.vis_cnt[x] : 0u;
-            uint32_t off = wave_bump(&ctl->cursor, cnt);
-            if (x < vadm) W.vis_off[x] = off;
-        } else {
-            uint32_t j = x - nB;
-            uint64_t e = W.act_list[j];
-            const VolDev &V = vols[(uint32_t)(e >> 32)];
-            uint32_t b = (uint32_t)e;
-            uint32_t s = V.map[b];
-            bool miss = s == NONE;
+    for (uint32_t x0 = blockIdx.x * 256u; x0 < K; x0 += gridDim.x * 256u) {
+        const uint32_t j = x0 + threadIdx.x;
+        bool miss = false;
+        uint64_t e = 0;
+        if (j < K) {
+            e = W.act_list[j];
+            const uint32_t s = vols[(uint32_t)(e >> 32)].map[(uint32_t)e];
+            miss = s == NONE;
             if (!miss) C.stamp[s] = pass;
-            uint32_t idx = wave_append(&ctl->n_miss, miss);
-            if (miss) W.miss_list[idx] = e;
         }
+        const uint32_t idx = block_bump<256>(&ctl->n_miss, miss ? 1u : 0u, s_tmp);
+        if (miss) W.miss_list[idx] = e;
     }
 }
 
@@ -695,6 +727,7 @@ __global__ __launch_bounds__(256) void k_lookup(PassCtl *ctl, const VolDev *vols
 // is evicted in one sweep.
 __global__ void k_alloc_plan(PassCtl *ctl) {
     if (threadIdx.x != 0) return;
+    ctl->served = ctl->cursor;   // the admitted blocks' runs cover exactly the served pairs
     uint32_t m = ctl->n_miss, f = ctl->free_top;
     if (m > f) {
         uint32_t short_by = m - f;
@@ -737,8 +770,13 @@ __global__ __launch_bounds__(256) void k_evict_hist(PassCtl *ctl, Cache C) {
 
 __global__ __launch_bounds__(256) void k_evict(PassCtl *ctl, const VolDev *vols, Cache C) {
     if (ctl->need == 0) return;
+    __shared__ uint32_t s_tmp[256 / 64 + 1];
+    __shared__ uint32_t s_ev;
     const uint32_t pass = ctl->pass, T = ctl->evict_T;
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < round64(C.n_slots); s += gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) s_ev = 0;
+    uint32_t my_ev = 0;
+    for (uint32_t s0 = blockIdx.x * 256u; s0 < C.n_slots; s0 += gridDim.x * 256u) {
+        const uint32_t s = s0 + threadIdx.x;
         bool ev = false;
         if (s < C.n_slots) {
             uint64_t o = C.owner[s];
@@ -752,11 +790,15 @@ __global__ __launch_bounds__(256) void k_evict(PassCtl *ctl, const VolDev *vols,
                 }
             }
         }
-        uint32_t idx = wave_append(&ctl->free_top, ev);
-        if (ev) C.free_stack[idx] = s;
-        uint64_t em = __ballot(ev);
-        if (lane_id() == 0 && em) atomicAdd(&ctl->evicted, (uint32_t)__popcll(em));
+        const uint32_t idx = block_bump<256>(&ctl->free_top, ev ? 1u : 0u, s_tmp);
+        if (ev) {
+            C.free_stack[idx] = s;
+            my_ev++;
+        }
     }
+    if (my_ev) atomicAdd(&s_ev, my_ev);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_ev) atomicAdd(&ctl->evicted, s_ev);
 }
 
 // ---------------------------------------------------------------- K5 ------
@@ -1042,63 +1084,100 @@ __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const 
             alive = !term;
             my_term = term ? 1u : 0u;
         }
-        uint64_t m = __ballot(alive);
-        if (lane_id() == 0) T.wave_cnt[p >> 6] = (uint32_t)__popcll(m);
-        // per-request counters (all lanes of a wave belong to one request)
-        uint32_t sp = my_pairs, sd = my_def, stt = my_term;
+        // per-wave record: survivors (for the compaction scan) and the
+        // request's pass counters, summed by k_pass_end
+        const uint64_t m = __ballot(alive);
+        uint32_t sp = my_pairs, sd = my_def;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             sp += __shfl_xor(sp, off);
             sd += __shfl_xor(sd, off);
-            stt += __shfl_xor(stt, off);
         }
-        if (lane_id() == 0) {
-            if (sp) {
-                atomicAdd(&st->last_pairs, sp);
-                atomicAdd(&st->tot_pairs, (unsigned long long)sp);
-                atomicAdd(&ctl->pairs, sp);
-            }
-            if (sd) atomicAdd(&st->last_deferred, sd);
-            if (stt) { atomicAdd(&st->last_terminated, stt); atomicAdd(&ctl->terminated, stt); }
-        }
+        const uint32_t nt = (uint32_t)__popcll(__ballot(my_term != 0));
+        if (lane_id() == 0) T.wave_rec[p >> 6] = make_uint4((uint32_t)__popcll(m), sp, sd, nt);
     }
 }
 
 // --------------------------------------------------------------- K11 ------
 // Count the surviving rays (Sec. 3 step (f)): exclusive scan of the per-wave
 // survivor counts, per-request N_act, N_spec = clamp(floor(w*h / N_act), 1,
-// cap) (Sec. 4), and flip to the other active-ray list.  One workgroup.
-__global__ __launch_bounds__(1024) void k_pass_end(PassCtl *ctl, Table T, int is_init) {
-    __shared__ uint32_t s_part[1024];
-    __shared__ uint32_t s_carry;
+// cap) (Sec. 4), the per-request pass counters, and the flip to the other
+// active-ray list.  One workgroup; each thread owns a contiguous run of waves,
+// sums it (splitting at request boundaries into LDS per-request sums), the
+// workgroup scans the run totals, and each thread writes its run's offsets.
+constexpr int PE_THREADS = 1024;
+
+__global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, int is_init) {
+    __shared__ uint32_t s_req[4][MAX_REQS];   // survivors, pairs, deferred, terminated
+    __shared__ uint32_t s_wave[PE_THREADS / 64];
     const uint32_t nw = ctl->A >> 6;
+    const uint32_t nreq = ctl->nreq;
     const uint32_t t = threadIdx.x;
-    if (t == 0) s_carry = 0;
-    __syncthreads();
-    for (uint32_t base = 0; base < nw; base += 1024) {
-        uint32_t v = base + t < nw ? T.wave_cnt[base + t] : 0u;
-        s_part[t] = v;
-        __syncthreads();
-        for (uint32_t off = 1; off < 1024; off <<= 1) {
-            uint32_t o = t >= off ? s_part[t - off] : 0u;
-            __syncthreads();
-            s_part[t] += o;
-            __syncthreads();
-        }
-        uint32_t incl = s_part[t];
-        if (base + t < nw) T.wave_off[base + t] = s_carry + incl - v;
-        __syncthreads();
-        if (t == 1023) s_carry += incl;
-        __syncthreads();
+    for (uint32_t r = t; r < nreq; r += PE_THREADS) {
+        s_req[0][r] = 0; s_req[1][r] = 0; s_req[2][r] = 0; s_req[3][r] = 0;
     }
+    __syncthreads();
+    const uint32_t per = (nw + PE_THREADS - 1) / PE_THREADS;
+    const uint32_t w0 = t * per < nw ? t * per : nw;
+    const uint32_t w1 = w0 + per < nw ? w0 + per : nw;
+    uint32_t run = 0;
+    if (w0 < w1) {
+        uint32_t r = find_req(T.act_base, nreq, w0 << 6);
+        uint32_t next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
+        uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+        for (uint32_t w = w0; w < w1; ++w) {
+            while (w >= next) {   // crossing into the next request's waves
+                if (acc.x) atomicAdd(&s_req[0][r], acc.x);
+                if (acc.y) atomicAdd(&s_req[1][r], acc.y);
+                if (acc.z) atomicAdd(&s_req[2][r], acc.z);
+                if (acc.w) atomicAdd(&s_req[3][r], acc.w);
+                acc = make_uint4(0u, 0u, 0u, 0u);
+                ++r;
+                next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
+            }
+            const uint4 v = T.wave_rec[w];
+            acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+        }
+        if (acc.x) atomicAdd(&s_req[0][r], acc.x);
+        if (acc.y) atomicAdd(&s_req[1][r], acc.y);
+        if (acc.z) atomicAdd(&s_req[2][r], acc.z);
+        if (acc.w) atomicAdd(&s_req[3][r], acc.w);
+        run = 0;
+        for (uint32_t w = w0; w < w1; ++w) run += T.wave_rec[w].x;
+    }
+    // workgroup exclusive scan of the run totals
+    const uint32_t l = lane_id(), wv = t >> 6;
+    uint32_t incl = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(incl, off);
+        if ((int)l >= off) incl += o;
+    }
+    if (l == 63) s_wave[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t k = 0; k < wv; ++k) before += s_wave[k];
+    uint32_t off = before + incl - run;
+    for (uint32_t w = w0; w < w1; ++w) {
+        T.wave_off[w] = off;
+        off += T.wave_rec[w].x;
+    }
+    if (t == PE_THREADS - 1) T.wave_off[nw] = off;   // == total survivors
+    __syncthreads();
     if (t == 0) {
-        T.wave_off[nw] = s_carry;
+        uint32_t pairs = 0, term = 0;
+        for (uint32_t r = 0; r < nreq; ++r) {
+            pairs += s_req[1][r];
+            term += s_req[3][r];
+        }
+        ctl->pairs = pairs;
+        ctl->terminated = term;
         if (!is_init && ctl->A > 0) {
             ctl->acc_passes += 1;
             ctl->acc_decoded += ctl->assigned;
             ctl->acc_visible += ctl->n_vis;
             ctl->acc_active += ctl->n_actblk;
-            ctl->acc_pairs += ctl->pairs;
+            ctl->acc_pairs += pairs;
             ctl->acc_evicted += ctl->evicted;
             ctl->acc_overflow += ctl->overflow;
             ctl->acc_rays += ctl->rays;
@@ -1106,14 +1185,16 @@ __global__ __launch_bounds__(1024) void k_pass_end(PassCtl *ctl, Table T, int is
             ctl->acc_served += ctl->served;
         }
     }
-    __syncthreads();
-    for (uint32_t r = t; r < ctl->nreq; r += blockDim.x) {
+    for (uint32_t r = t; r < nreq; r += PE_THREADS) {
         ReqDev &q = T.reqs[r];
         ReqState *st = q.st;
-        uint32_t w0 = T.act_base[r] >> 6, w1 = T.act_base[r + 1] >> 6;
-        uint32_t na = (w1 > w0 ? (w1 < nw ? T.wave_off[w1] : s_carry) - T.wave_off[w0] : 0u);
+        const uint32_t na = s_req[0][r];
         if (st->n_act_prev > 0) st->cur ^= 1u;
         st->n_act = na;
+        st->last_pairs = s_req[1][r];
+        st->last_deferred = s_req[2][r];
+        st->last_terminated = s_req[3][r];
+        st->tot_pairs += s_req[1][r];
         uint32_t ns = 0;
         if (na > 0) {
             ns = q.npix / na;
@@ -1229,8 +1310,8 @@ hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev
     };
     mark(); hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, ctl, T, 0);
     mark(); hipLaunchKernelGGL(k_traverse, dim3(g.rays), dim3(256), 0, s, ctl, T, vols);
-    mark(); hipLaunchKernelGGL(k_dedupe, dim3(g.pairs), dim3(256), 0, s, ctl, T, vols, W);
-    mark(); hipLaunchKernelGGL(k_mark, dim3(g.pairs), dim3(256), 0, s, ctl, T, vols, W);
+    mark(); hipLaunchKernelGGL(k_dedupe, dim3(g.dedupe), dim3(256), 0, s, ctl, T, vols, W);
+    mark(); hipLaunchKernelGGL(k_mark, dim3(g.pairs), dim3(256), 0, s, ctl, vols, W);
     mark(); hipLaunchKernelGGL(k_lookup, dim3(g.blocks), dim3(256), 0, s, ctl, vols, W, C);
     mark(); hipLaunchKernelGGL(k_alloc_plan, dim3(1), dim3(64), 0, s, ctl);
     mark(); hipLaunchKernelGGL(k_evict_hist, dim3(g.slots), dim3(256), 0, s, ctl, C);

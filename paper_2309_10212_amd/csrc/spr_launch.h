@@ -11,6 +11,7 @@ namespace spr {
 struct PassGrids {
     uint32_t rays;      // 256-thread groups over the active-ray space
     uint32_t pairs;     // 256-thread groups over the pair space
+    uint32_t dedupe;    // 256-thread groups over the pair space, DD_ITEMS pairs per thread
     uint32_t blocks;    // 256-thread groups over visible/active/miss lists
     uint32_t slots;     // 256-thread groups over cache slots (eviction sweeps)
     uint32_t assign;    // 256-thread groups assigning slots to misses

@@ -165,10 +165,13 @@ def test_speculation_and_cache_size_do_not_change_the_image(ctx):
     vol2 = small.load_volume(s, (64, 64, 64), 8)
     r = spr.Render(vol2, cam, 0.5, 128, 96, spec_cap=8)
     deferred = 0
+    passes = 0
     while not r.done():
         st = r.pass_(stats=True)
         deferred += st["deferred"]
+        passes += 1
         assert st["active_blocks"] <= 40
+        assert passes < 5000, "no progress under deferral"
     outs.append((r.hits(), r.image()))
     assert deferred > 0
     r.free()
