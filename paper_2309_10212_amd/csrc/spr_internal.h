@@ -160,6 +160,52 @@ struct Cache {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Wave-uniform values in scalar registers.  Fields read through generic
+// pointers are otherwise treated as per-lane and kept in vector registers
+// (or re-loaded inside loops); every caller guarantees the value is the same
+// across the wave.
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x) { return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(x))); }
+// readfirstlane returns int: both halves are zero-extended (a sign-extended
+// low word would set the upper 32 bits of every value with bit 31 set).
+__device__ __forceinline__ uint64_t uni(uint64_t x) {
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+__device__ __forceinline__ double uni(double x) { return __longlong_as_double((long long)uni((uint64_t)__double_as_longlong(x))); }
+template <class T>
+__device__ __forceinline__ T *uni(T *p) { return (T *)uni((uint64_t)p); }
+
+// Device-memory pointers read from structures are generic (flat) pointers;
+// flat accesses count against both the memory and the LDS wait counters.
+// Casting to the global address space gives global_* instructions, which a
+// later LDS wait does not have to drain.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T *p) { return (gptr<T>)p; }
+
+// The camera and volume fields one wave needs, read once into scalar
+// registers (all lanes of a wave serve the same request).
+struct WaveReq {
+    double eye[3], fwd[3], right[3], upv[3];
+    double sx, sy;
+    uint32_t w, h;
+    int n[3], nb[3], nc[3], tb[3], tc[3];
+};
+
+__device__ __forceinline__ void load_wave_req(const ReqDev &q, const VolDev &V, WaveReq &u) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u.eye[a] = uni(q.eye[a]); u.fwd[a] = uni(q.fwd[a]); u.right[a] = uni(q.right[a]); u.upv[a] = uni(q.upv[a]);
+        u.n[a] = uni(V.n[a]); u.nb[a] = uni(V.nb[a]); u.nc[a] = uni(V.nc[a]); u.tb[a] = uni(V.tb[a]); u.tc[a] = uni(V.tc[a]);
+    }
+    u.sx = uni(q.sx); u.sy = uni(q.sy);
+    u.w = uni(q.w); u.h = uni(q.h);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     uint32_t l = lane_id();
     return l == 0 ? 0ull : (~0ull >> (64 - l));
@@ -231,7 +277,8 @@ struct Ray {
 
 __device__ __forceinline__ double tau_at(const Ray &R, int a, int m) { return ((double)m - R.o[a]) * R.r[a]; }
 
-__device__ inline void make_ray(const ReqDev &q, const int n[3], uint32_t pix, Ray &R) {
+template <class Cam>
+__device__ inline void make_ray(const Cam &q, const int n[3], uint32_t pix, Ray &R) {
     int px = (int)(pix % q.w), py = (int)(pix / q.w);
     double ndx = (2.0 * ((double)px + 0.5)) / (double)q.w - 1.0;
     double ndy = 1.0 - (2.0 * ((double)py + 0.5)) / (double)q.h;
@@ -339,6 +386,58 @@ __device__ __forceinline__ double cell_entry(const Ray &R, const Level &lv, cons
         else if (R.d[a] < 0.0) { double e = tau_plane(R, lv, a, c[a] + 1); if (e > t0) t0 = e; }
     }
     return t0;
+}
+
+// Incremental walk at one level.  Per axis: the step direction and the
+// parameter of the current cell's exit plane (+inf where the ray is parallel
+// to the axis), the same plane parameters cell_exit computes; a step only
+// recomputes the axes that move, with selects instead of per-axis branches.
+struct AxisWalk {
+    int dir[3];
+    double tex[3];
+};
+
+__device__ __forceinline__ double exit_tau(const Ray &R, const Level &lv, int a, int dir, int c) {
+    const double t = tau_plane(R, lv, a, c + (dir > 0 ? 1 : 0));
+    return dir != 0 ? t : __builtin_inf();
+}
+
+__device__ __forceinline__ void walk_init(const Ray &R, const Level &lv, const int c[3], AxisWalk &w) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        w.dir[a] = R.d[a] > 0.0 ? 1 : (R.d[a] < 0.0 ? -1 : 0);
+        w.tex[a] = exit_tau(R, lv, a, w.dir[a], c[a]);
+    }
+}
+
+// exit parameter of the current cell: cell_exit's minimum
+__device__ __forceinline__ double walk_exit(const AxisWalk &w) {
+    double tn = w.tex[0];
+    tn = w.tex[1] < tn ? w.tex[1] : tn;
+    tn = w.tex[2] < tn ? w.tex[2] : tn;
+    return tn;
+}
+
+// Cross every plane with parameter <= tn (tied planes together); false when
+// the ray leaves [lo, hi] on some axis.  The same cell and result as
+// advance(): each axis moves independently of the others, and a second round
+// only runs when two consecutive planes of an axis round to parameters <= tn.
+__device__ __forceinline__ bool walk_step(const Ray &R, const Level &lv, AxisWalk &w, int c[3], double tn,
+                                          const int lo[3], const int hi[3]) {
+    bool ok = true;
+    for (int round = 0; round < 8; ++round) {
+        bool again = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool st = w.tex[a] <= tn;
+            c[a] += st ? w.dir[a] : 0;
+            ok = ok && !(st && (c[a] < lo[a] || c[a] > hi[a]));
+            w.tex[a] = st ? exit_tau(R, lv, a, w.dir[a], c[a]) : w.tex[a];
+            again = again || (st && w.tex[a] <= tn);
+        }
+        if (!again || !ok) break;
+    }
+    return ok;
 }
 
 // Cross every plane with tau <= tn.  Returns false when the ray leaves

@@ -32,23 +32,14 @@ __constant__ OrderTable c_order = make_order();
 
 // --------------------------------------------------- codec: thread decode --
 // One thread decodes one block, bit by bit, in the order the format defines
-// (the same control flow as the encoder, mirrored).  The record words sit in
-// registers and the next word is picked by an unrolled select (no dynamic
-// register indexing); magnitudes of the order-space coefficients live in LDS,
-// interleaved so that a wave touching coefficient j hits 64 distinct banks;
-// the significance mask and the sign mask are 64-bit registers.  The inverse
-// integer transform then runs on 64 int32 values in registers with
-// compile-time indices.
+// (the same control flow as the encoder, mirrored).  The record words are
+// staged in LDS and the next one is prefetched a word ahead; magnitudes of the
+// order-space coefficients live in LDS, interleaved so that a wave touching
+// coefficient j hits distinct banks; the significance and sign masks are
+// 64-bit registers.  The inverse integer transform then runs on 64 int32
+// values in registers with compile-time indices.
 
 static constexpr OrderTable kOrder = make_order();
-
-template <int RWMAX>
-__device__ __forceinline__ uint32_t pick_word(const uint32_t (&w)[RWMAX], uint32_t i) {
-    uint32_t r = 0;
-#pragma unroll
-    for (int j = 0; j < RWMAX; ++j) r = (uint32_t)j == i ? w[j] : r;
-    return r;
-}
 
 // 32-bit two's complement lifting (the codec's integer arithmetic): sums
 // wrap modulo 2^32 (done in unsigned arithmetic), halving is an arithmetic
@@ -68,85 +59,104 @@ __device__ __forceinline__ void inv4(int32_t &p0, int32_t &p1, int32_t &p2, int3
     p0 = a0; p1 = a1; p2 = a2; p3 = a3;
 }
 
+// Per-wave LDS of the thread decoder: record words (RWMAX + 2 per lane, the
+// tail reads as 0) and 64 magnitudes per lane.
+template <int RWMAX>
+struct DecodeLds {
+    uint32_t rec[(RWMAX + 2) * 64];
+    uint32_t mag[64 * 64];
+};
+
+__device__ __forceinline__ uint32_t low_bit(uint64_t x) { return (uint32_t)__ffsll((unsigned long long)x) - 1u; }
+
 // Decodes the record into q[64] (raster order) and the block exponent.
-// Returns false for an all-zero block (q untouched).  s_mag: this wave's
-// 64x64 u32 LDS area; lane: lane id within the wave.
+// Returns false for an all-zero block (q untouched).  L: this wave's LDS;
+// lane: lane id within the wave; rate: 1..16 bits per value (RWMAX >= 2 rate).
 //
 // The decoder is one flat loop in which every active lane consumes exactly
 // one bit per iteration; the meaning of the bit depends on the lane's mode:
-//   REF   refinement bit of the next significant coefficient (mask R),
-//   GT    group test over the candidates from the cursor (mask C),
-//   SCAN  next candidate's plane bit (mask I), the first 1 is the target,
-//   SIGN  the target's sign; it becomes significant.
-// Transitions that consume no bit (end of refinement, no candidate left, next
-// plane) are settled after each bit.  Lanes decoding different blocks stay in
-// lockstep: a wave takes about as many iterations as one block has bits.
+//   REF   refinement bit of the next significant coefficient,
+//   GT    group test over the candidates (insignificant coefficients at or
+//         after the cursor c),
+//   SCAN  next candidate's plane bit, the first 1 is the target,
+//   SIGN  the target's sign; it becomes significant and c moves past it.
+// One work mask W holds the coefficients still to visit in REF (significant
+// ones) and in SCAN (candidates).  The transitions that consume no bit (end
+// of refinement, no candidate left, next plane) need at most one settle step,
+// and every update is a select, so the loop body has a single branch (around
+// the LDS update).  Lanes decoding different blocks stay in lockstep: a wave
+// takes about as many iterations as one block has bits.
 enum : uint32_t { M_REF = 0, M_GT = 1, M_SCAN = 2, M_SIGN = 3, M_DONE = 4 };
 
 template <int RWMAX>
-__device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, int rate, uint32_t *s_mag,
+__device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, int rate, DecodeLds<RWMAX> &L,
                                               uint32_t lane, int32_t (&q)[64], int &e_out) {
     const uint32_t rw = 2u * (uint32_t)rate;
-    uint32_t w[RWMAX];
+    const uint32_t w0 = rec[0];
+    if (!(w0 & 1u)) return false;
 #pragma unroll
-    for (int j = 0; j < RWMAX; ++j) w[j] = (uint32_t)j < rw ? rec[j] : 0u;
-    if (!(w[0] & 1u)) return false;
-    e_out = (int)((w[0] >> 1) & 0xFFu) - 127;
+    for (int j = 1; j < RWMAX + 2; ++j) L.rec[j * 64 + lane] = (uint32_t)j < rw ? rec[j] : 0u;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) L.mag[j * 64 + lane] = 0u;
+    e_out = (int)((w0 >> 1) & 0xFFu) - 127;
     const uint32_t B = 64u * (uint32_t)rate;
-    uint64_t buf = ((uint64_t)w[0] | ((uint64_t)w[1] << 32)) >> 9;
+    // buf holds nbits >= 32 unread bits; refills take the next word when it
+    // drops below 32; at most rw - 1 refills happen before pos reaches B, so
+    // wi stays <= rw + 1 <= RWMAX + 1
+    uint64_t buf = ((uint64_t)w0 | ((uint64_t)L.rec[64 + lane] << 32)) >> 9;
     uint32_t nbits = 55, wi = 2, pos = 9;
-    uint64_t S = 0, NEG = 0, R = 0, C = ~0ull, I = 0;
+    uint32_t nxt = L.rec[2 * 64 + lane];
+    uint64_t S = 0, NEG = 0, W = 0;
+    uint32_t c = 0, t = 0;
     int k = 29;
-    uint32_t mode = M_GT, t = 0;   // plane 29 has nothing to refine
-    for (;;) {
-        if (mode == M_DONE || pos >= B) break;
-        const uint32_t bit = (uint32_t)(buf & 1ull);
+    uint32_t mode = M_GT;   // plane 29 has nothing to refine; every coefficient is a candidate
+    while (mode != M_DONE && pos < B) {
+        const uint32_t bit = (uint32_t)buf & 1u;
         buf >>= 1;
         --nbits;
         ++pos;
-        if (nbits < 32) {
-            buf |= (uint64_t)pick_word<RWMAX>(w, wi) << nbits;
-            nbits += 32;
-            ++wi;
+        const bool need = nbits < 32u;
+        buf |= need ? ((uint64_t)nxt << nbits) : 0ull;
+        nbits += need ? 32u : 0u;
+        wi += need ? 1u : 0u;
+        nxt = L.rec[wi * 64 + lane];
+
+        const bool isREF = mode == M_REF, isGT = mode == M_GT, isSCAN = mode == M_SCAN, isSIGN = mode == M_SIGN;
+        const uint32_t j = (uint32_t)__builtin_ctzll(W | (1ull << 63));   // W != 0 in REF and SCAN
+        if (isREF || isSIGN) {
+            const uint32_t at = isREF ? j : t;
+            const uint32_t v = (isREF ? bit : 1u) << k;
+            __hip_atomic_fetch_or(&L.mag[at * 64 + lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
-        bool next_plane = false;
-        if (mode == M_REF) {
-            uint32_t j = (uint32_t)__ffsll((unsigned long long)R) - 1u;
-            R &= R - 1ull;
-            if (bit) s_mag[j * 64 + lane] |= 1u << k;
-            if (R == 0) { mode = M_GT; C = ~S; }
-        } else if (mode == M_GT) {
-            if (bit) { mode = M_SCAN; I = C; }
-            else next_plane = true;
-        } else if (mode == M_SCAN) {
-            uint32_t j = (uint32_t)__ffsll((unsigned long long)I) - 1u;
-            I &= I - 1ull;
-            if (bit) { mode = M_SIGN; t = j; }
-            else if (I == 0) mode = M_DONE;   // no candidate had the bit: not a valid record
-        } else {   // M_SIGN
-            NEG |= (uint64_t)bit << t;
-            s_mag[t * 64 + lane] = 1u << k;
-            S |= 1ull << t;
-            mode = M_GT;
-            C = t >= 63 ? 0ull : (~S & (~0ull << (t + 1)));
-        }
-        // settle the transitions that read no bit
-        for (int guard = 0; guard < 4; ++guard) {
-            if (mode == M_GT && C == 0) next_plane = true;
-            if (!next_plane) break;
-            next_plane = false;
-            if (--k < 0) { mode = M_DONE; break; }
-            if (S) { mode = M_REF; R = S; }
-            else { mode = M_GT; C = ~0ull; }
-        }
+        const uint64_t Wn = W & (W - 1ull);
+        const bool ref_end = isREF && Wn == 0ull;
+        const bool scan_hit = isSCAN && bit;
+        const bool scan_fail = isSCAN && !bit && Wn == 0ull;
+        const uint64_t tbit = 1ull << t;
+        S |= isSIGN ? tbit : 0ull;
+        NEG |= (isSIGN && bit) ? tbit : 0ull;
+        c = isSIGN ? t + 1u : (ref_end ? 0u : c);
+        const uint64_t cand = c >= 64u ? 0ull : (~S & (~0ull << c));
+        W = (isREF || isSCAN) ? Wn : ((isGT && bit) ? cand : W);
+        t = scan_hit ? j : t;
+        uint32_t nm = mode;
+        nm = ref_end ? M_GT : nm;
+        nm = (isGT && bit) ? M_SCAN : nm;
+        nm = scan_hit ? M_SIGN : (scan_fail ? M_DONE : nm);
+        nm = isSIGN ? M_GT : nm;
+        // settle: a group test with no candidate left ends the plane
+        const bool np = (isGT && !bit) || (nm == M_GT && cand == 0ull);
+        const int kn = np ? k - 1 : k;
+        W = np ? S : W;
+        c = np ? 0u : c;
+        nm = np ? (kn < 0 ? M_DONE : (S != 0ull ? M_REF : M_GT)) : nm;
+        k = kn;
+        mode = nm;
     }
 #pragma unroll
     for (int j = 0; j < 64; ++j) {
-        int32_t v = 0;   // magnitudes are below 2^30
-        if ((S >> j) & 1ull) {
-            v = (int32_t)s_mag[j * 64 + lane];
-            if ((NEG >> j) & 1ull) v = -v;
-        }
+        int32_t v = (int32_t)L.mag[j * 64 + lane];   // magnitudes are below 2^30; 0 if never significant
+        if ((NEG >> j) & 1ull) v = -v;
         q[kOrder.ord[j]] = v;
     }
 #pragma unroll
@@ -166,7 +176,7 @@ __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, 
 
 // Decode one block to 64 floats, stored with 16-byte stores to dst (raster order).
 template <int RWMAX>
-__device__ __forceinline__ void decode_to(const uint32_t *__restrict__ rec, int rate, uint32_t *s_mag, uint32_t lane,
+__device__ __forceinline__ void decode_to(const uint32_t *__restrict__ rec, int rate, DecodeLds<RWMAX> &L, uint32_t lane,
                                           float *__restrict__ dst) {
     float4 *d4 = reinterpret_cast<float4 *>(dst);
     if (rate == 32) {
@@ -177,7 +187,7 @@ __device__ __forceinline__ void decode_to(const uint32_t *__restrict__ rec, int 
     }
     int32_t q[64];
     int e = 0;
-    if (!thread_decode<RWMAX>(rec, rate, s_mag, lane, q, e)) {
+    if (!thread_decode<RWMAX>(rec, rate, L, lane, q, e)) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) d4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         return;
@@ -201,11 +211,11 @@ __device__ __forceinline__ void decode_to(const uint32_t *__restrict__ rec, int 
 
 // Decode listed blocks of one volume into out[i*64 ..] (debug/parity path).
 __global__ __launch_bounds__(64) void k_decode_ids(VolDev V, const uint32_t *ids, uint32_t n, float *out) {
-    __shared__ uint32_t s_mag[64 * 64];
+    __shared__ DecodeLds<32> L;
     const uint32_t lane = threadIdx.x;
     for (uint32_t i = blockIdx.x * 64 + lane; i < n; i += gridDim.x * 64) {
         const uint32_t *rec = V.stream + (size_t)ids[i] * (size_t)V.rec_words;
-        decode_to<32>(rec, V.rate, s_mag, lane, out + (size_t)i * 64);
+        decode_to<32>(rec, V.rate, L, lane, out + (size_t)i * 64);
     }
 }
 
@@ -213,7 +223,7 @@ __global__ __launch_bounds__(64) void k_decode_ids(VolDev V, const uint32_t *ids
 // samples inside the volume (Sec. 3.1).
 template <int RWMAX>
 __global__ __launch_bounds__(64) void k_block_ranges(VolDev V, float2 *blk) {
-    __shared__ uint32_t s_mag[64 * 64];
+    __shared__ DecodeLds<RWMAX> L;
     const uint32_t lane = threadIdx.x;
     for (uint64_t b = blockIdx.x * 64ull + lane; b < V.nblocks; b += (uint64_t)gridDim.x * 64) {
         const uint32_t *rec = V.stream + b * (uint64_t)V.rec_words;
@@ -237,7 +247,7 @@ __global__ __launch_bounds__(64) void k_block_ranges(VolDev V, float2 *blk) {
         } else {
             int32_t q[64];
             int e = 0;
-            if (!thread_decode<RWMAX>(rec, V.rate, s_mag, lane, q, e)) {
+            if (!thread_decode<RWMAX>(rec, V.rate, L, lane, q, e)) {
                 lo = 0.0f;
                 hi = 0.0f;
             } else {
@@ -465,32 +475,43 @@ __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
 
 __device__ __forceinline__ bool range_has(float2 r, float iso) { return r.x <= iso && iso <= r.y; }
 
-__global__ __launch_bounds__(256, 5) void k_traverse(PassCtl *ctl, Table T, const VolDev *vols) {
+// Candidates are staged in LDS and written out after the walk (or when
+// TR_BUF have accumulated): on this architecture one counter tracks vector
+// loads and stores alike, so a store inside the walk would make the next
+// mask load wait for the store's completion as well.
+constexpr uint32_t TR_BUF = 16;
+
+__global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const VolDev *vols) {
+    __shared__ uint32_t s_slot[TR_BUF][256];
     const uint32_t A = ctl->A;
+    const uint32_t nreq = ctl->nreq;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
         // all lanes of a wave share a request (the A space is 64-aligned per request)
-        uint32_t r = __builtin_amdgcn_readfirstlane(find_req(T.act_base, ctl->nreq, p));
+        const uint32_t r = uni(find_req(T.act_base, nreq, p));
         const ReqDev &q = T.reqs[r];
-        const ReqState *st = q.st;
-        uint32_t i = p - T.act_base[r];
-        if (i >= st->n_act_prev) continue;
-        const uint32_t ns = st->last_nspec;
-        const uint32_t pix = q.act[st->cur][i];
-        const VolDev &V = vols[q.vol];
+        const ReqState *st = uni(q.st);
+        const uint32_t i = p - uni(T.act_base[r]);
+        if (i >= uni(st->n_act_prev)) continue;
+        const uint32_t ns = uni(st->last_nspec);
+        const uint32_t pix = uni(q.act[uni(st->cur)])[i];
+        WaveReq u;
+        load_wave_req(q, vols[uni(q.vol)], u);
+        const gptr<const uint64_t> cmask = as_global((const uint64_t *)uni(q.cmask64));
+        const gptr<uint32_t> slots = as_global(uni(q.pair_blk) + (size_t)i * ns);
+        const uint32_t state = uni(q.ray_state)[pix];
         Ray R;
-        make_ray(q, V.n, pix, R);
-        uint32_t *slots = q.pair_blk + (size_t)i * ns;
-        Level LB = {4, {V.tb[0], V.tb[1], V.tb[2]}, {V.n[0], V.n[1], V.n[2]}};
-        Level LC = {16, {V.tc[0], V.tc[1], V.tc[2]}, {V.n[0], V.n[1], V.n[2]}};
+        make_ray(u, u.n, pix, R);
+        Level LB = {4, {u.tb[0], u.tb[1], u.tb[2]}, {u.n[0], u.n[1], u.n[2]}};
+        Level LC = {16, {u.tc[0], u.tc[1], u.tc[2]}, {u.n[0], u.n[1], u.n[2]}};
         const int zero3[3] = {0, 0, 0};
-        const int tbhi[3] = {V.tb[0] - 1, V.tb[1] - 1, V.tb[2] - 1};
-        const int tchi[3] = {V.tc[0] - 1, V.tc[1] - 1, V.tc[2] - 1};
+        const int tbhi[3] = {u.tb[0] - 1, u.tb[1] - 1, u.tb[2] - 1};
+        const int tchi[3] = {u.tc[0] - 1, u.tc[1] - 1, u.tc[2] - 1};
         int cb[3], cc[3];
+        AxisWalk wb;   // block-level walk state, valid while bvalid
         double tcur;
         bool bvalid, ctest;
         bool alive = true;
         uint32_t found = 0;
-        const uint32_t state = q.ray_state[pix];
         if (state == RAY_NOT_STARTED) {
             tcur = R.te;
 #pragma unroll
@@ -499,27 +520,27 @@ __global__ __launch_bounds__(256, 5) void k_traverse(PassCtl *ctl, Table T, cons
             ctest = true;
         } else {
             uint32_t b = state;
-            cb[0] = (int)(b % (uint32_t)V.nb[0]);
-            cb[1] = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
-            cb[2] = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
-#pragma unroll
-            for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
-            double tn = cell_exit(R, LB, cb);
-            if (tn > R.tx || !advance(R, LB, cb, tn, zero3, tbhi)) alive = false;
+            cb[0] = (int)(b % (uint32_t)u.nb[0]);
+            cb[1] = (int)((b / (uint32_t)u.nb[0]) % (uint32_t)u.nb[1]);
+            cb[2] = (int)(b / ((uint32_t)u.nb[0] * (uint32_t)u.nb[1]));
+            walk_init(R, LB, cb, wb);
+            double tn = walk_exit(wb);
+            if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) alive = false;
             tcur = tn;
             bvalid = true;
             ctest = true;   // (re)load the coarse cell's block bits
 #pragma unroll
             for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
         }
+        uint32_t nbuf = 0, flushed = 0;   // candidates staged in LDS / already written
         uint64_t cm = 0;
-        const int max_steps = V.tb[0] + V.tb[1] + V.tb[2] + V.tc[0] + V.tc[1] + V.tc[2] + 8;
+        const int max_steps = u.tb[0] + u.tb[1] + u.tb[2] + u.tc[0] + u.tc[1] + u.tc[2] + 8;
         int steps = 0;
         while (alive && found < ns) {
             if (++steps > max_steps) { alive = false; break; }   // every step advances an index
             if (ctest) {
-                const uint64_t cid = ((uint64_t)cc[2] * V.nc[1] + cc[1]) * V.nc[0] + cc[0];
-                cm = q.cmask64[cid];
+                const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
+                cm = cmask[cid];
                 if (cm != 0) {
                     if (!bvalid) {
 #pragma unroll
@@ -528,6 +549,7 @@ __global__ __launch_bounds__(256, 5) void k_traverse(PassCtl *ctl, Table T, cons
                             if (hi > tbhi[a]) hi = tbhi[a];
                             cb[a] = cell_at(R, LB, a, tcur, lo, hi);
                         }
+                        walk_init(R, LB, cb, wb);
                         bvalid = true;
                     }
                     ctest = false;
@@ -541,13 +563,18 @@ __global__ __launch_bounds__(256, 5) void k_traverse(PassCtl *ctl, Table T, cons
             }
             const bool emit = (cm >> local_bit(cb)) & 1ull;
             if (emit) {
-                const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * V.nb[1] + cb[1]) * V.nb[0] + cb[0]);
-                slots[found] = bid;
+                const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * u.nb[1] + cb[1]) * u.nb[0] + cb[0]);
+                s_slot[nbuf][threadIdx.x] = bid;
                 found++;
+                if (++nbuf == TR_BUF) {
+                    for (uint32_t k = 0; k < TR_BUF; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
+                    flushed += TR_BUF;
+                    nbuf = 0;
+                }
                 if (found == ns) break;
             }
-            double tn = cell_exit(R, LB, cb);
-            if (tn > R.tx || !advance(R, LB, cb, tn, zero3, tbhi)) { alive = false; break; }
+            double tn = walk_exit(wb);
+            if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) { alive = false; break; }
             tcur = tn;
             if ((cb[0] >> 2) != cc[0] || (cb[1] >> 2) != cc[1] || (cb[2] >> 2) != cc[2]) {
 #pragma unroll
@@ -555,6 +582,7 @@ __global__ __launch_bounds__(256, 5) void k_traverse(PassCtl *ctl, Table T, cons
                 ctest = true;
             }
         }
+        for (uint32_t k = 0; k < nbuf; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
         for (uint32_t k = found; k < ns; ++k) slots[k] = NONE;
         // The block of pair 0 (the first active ray's first candidate) takes
         // visible-list index 0, so it is always admitted and every pass makes
@@ -851,13 +879,13 @@ __global__ __launch_bounds__(256) void k_assign_scatter(PassCtl *ctl, Table T, c
 // ---------------------------------------------------------------- K6 ------
 // Decode the misses into their slots (Sec. 3.5), one thread per block.
 __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols, Work W, Cache C) {
-    __shared__ uint32_t s_mag[64 * 64];
+    __shared__ DecodeLds<32> L;
     const uint32_t m = ctl->assigned;
     for (uint32_t i = blockIdx.x * 64 + threadIdx.x; i < m; i += gridDim.x * 64) {
         uint64_t e = W.miss_list[i];
         const VolDev &V = vols[(uint32_t)(e >> 32)];
         const uint32_t *rec = V.stream + (uint64_t)(uint32_t)e * (uint64_t)V.rec_words;
-        decode_to<32>(rec, V.rate, s_mag, threadIdx.x, C.slots + (size_t)W.miss_slot[i] * 64);
+        decode_to<32>(rec, V.rate, L, threadIdx.x, C.slots + (size_t)W.miss_slot[i] * 64);
     }
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->free_top -= m;   // the assigned slots leave the free stack
