@@ -329,6 +329,7 @@ struct Level {
     int S;
     int L[3];
     int n[3];
+    double invS;   // 1/S, exact: S is 1, 4 or 16
 };
 
 __device__ __forceinline__ int plane_pos(const Level &lv, int a, int m) {
@@ -353,7 +354,8 @@ __device__ __forceinline__ int still_cell(const Ray &R, const Level &lv, int a) 
 __device__ inline int cell_at(const Ray &R, const Level &lv, int a, double t, int lo, int hi) {
     if (R.d[a] == 0.0) return still_cell(R, lv, a);
     double p = R.o[a] + t * R.d[a];
-    int g = (int)floor(p / (double)lv.S);
+    int g = (int)floor(p * lv.invS);   // == floor(p / S): S is a power of two
+
     if (g < lo) g = lo;
     if (g > hi) g = hi;
     if (R.d[a] > 0.0) {
@@ -388,26 +390,26 @@ __device__ __forceinline__ double cell_entry(const Ray &R, const Level &lv, cons
     return t0;
 }
 
-// Incremental walk at one level.  Per axis: the step direction and the
-// parameter of the current cell's exit plane (+inf where the ray is parallel
-// to the axis), the same plane parameters cell_exit computes; a step only
-// recomputes the axes that move, with selects instead of per-axis branches.
+// Incremental walk at one level: per axis the parameter of the current
+// cell's exit plane (+inf where the ray is parallel to the axis), the same
+// plane parameters cell_exit computes; a step only recomputes the axes that
+// move, with selects instead of per-axis branches.  The step direction comes
+// from the sign of d each time (no extra registers).
 struct AxisWalk {
-    int dir[3];
     double tex[3];
 };
 
-__device__ __forceinline__ double exit_tau(const Ray &R, const Level &lv, int a, int dir, int c) {
+__device__ __forceinline__ int axis_dir(const Ray &R, int a) { return R.d[a] > 0.0 ? 1 : (R.d[a] < 0.0 ? -1 : 0); }
+
+__device__ __forceinline__ double exit_tau(const Ray &R, const Level &lv, int a, int c) {
+    const int dir = axis_dir(R, a);
     const double t = tau_plane(R, lv, a, c + (dir > 0 ? 1 : 0));
     return dir != 0 ? t : __builtin_inf();
 }
 
 __device__ __forceinline__ void walk_init(const Ray &R, const Level &lv, const int c[3], AxisWalk &w) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        w.dir[a] = R.d[a] > 0.0 ? 1 : (R.d[a] < 0.0 ? -1 : 0);
-        w.tex[a] = exit_tau(R, lv, a, w.dir[a], c[a]);
-    }
+    for (int a = 0; a < 3; ++a) w.tex[a] = exit_tau(R, lv, a, c[a]);
 }
 
 // exit parameter of the current cell: cell_exit's minimum
@@ -430,9 +432,9 @@ __device__ __forceinline__ bool walk_step(const Ray &R, const Level &lv, AxisWal
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool st = w.tex[a] <= tn;
-            c[a] += st ? w.dir[a] : 0;
+            c[a] += st ? axis_dir(R, a) : 0;
             ok = ok && !(st && (c[a] < lo[a] || c[a] > hi[a]));
-            w.tex[a] = st ? exit_tau(R, lv, a, w.dir[a], c[a]) : w.tex[a];
+            w.tex[a] = st ? exit_tau(R, lv, a, c[a]) : w.tex[a];
             again = again || (st && w.tex[a] <= tn);
         }
         if (!again || !ok) break;

@@ -501,15 +501,16 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         const uint32_t state = uni(q.ray_state)[pix];
         Ray R;
         make_ray(u, u.n, pix, R);
-        Level LB = {4, {u.tb[0], u.tb[1], u.tb[2]}, {u.n[0], u.n[1], u.n[2]}};
-        Level LC = {16, {u.tc[0], u.tc[1], u.tc[2]}, {u.n[0], u.n[1], u.n[2]}};
+        Level LB = {4, {u.tb[0], u.tb[1], u.tb[2]}, {u.n[0], u.n[1], u.n[2]}, 0.25};
+        Level LC = {16, {u.tc[0], u.tc[1], u.tc[2]}, {u.n[0], u.n[1], u.n[2]}, 0.0625};
         const int zero3[3] = {0, 0, 0};
         const int tbhi[3] = {u.tb[0] - 1, u.tb[1] - 1, u.tb[2] - 1};
         const int tchi[3] = {u.tc[0] - 1, u.tc[1] - 1, u.tc[2] - 1};
         int cb[3], cc[3];
         AxisWalk wb;   // block-level walk state, valid while bvalid
+        AxisWalk wc;   // coarse-level walk state, valid while cvalid
         double tcur;
-        bool bvalid, ctest;
+        bool bvalid, ctest, cvalid = false;
         bool alive = true;
         uint32_t found = 0;
         if (state == RAY_NOT_STARTED) {
@@ -554,8 +555,13 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                     }
                     ctest = false;
                 } else {
-                    double tn = cell_exit(R, LC, cc);
-                    if (tn > R.tx || !advance(R, LC, cc, tn, zero3, tchi)) { alive = false; break; }
+                    // empty coarse cell: step over it at the coarse level
+                    if (!cvalid) {
+                        walk_init(R, LC, cc, wc);
+                        cvalid = true;
+                    }
+                    double tn = walk_exit(wc);
+                    if (tn > R.tx || !walk_step(R, LC, wc, cc, tn, zero3, tchi)) { alive = false; break; }
                     tcur = tn;
                     bvalid = false;
                     continue;
@@ -580,6 +586,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
 #pragma unroll
                 for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
                 ctest = true;
+                cvalid = false;
             }
         }
         for (uint32_t k = 0; k < nbuf; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
@@ -998,8 +1005,8 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
             }
             Ray R;
             make_ray(q, V.n, pix, R);
-            Level LB = {4, {V.tb[0], V.tb[1], V.tb[2]}, {V.n[0], V.n[1], V.n[2]}};
-            Level L1 = {1, {V.n[0] - 1, V.n[1] - 1, V.n[2] - 1}, {V.n[0], V.n[1], V.n[2]}};
+            Level LB = {4, {V.tb[0], V.tb[1], V.tb[2]}, {V.n[0], V.n[1], V.n[2]}, 0.25};
+            Level L1 = {1, {V.n[0] - 1, V.n[1] - 1, V.n[2] - 1}, {V.n[0], V.n[1], V.n[2]}, 1.0};
             int lo[3], hi[3], c[3];
             double tb0 = cell_entry(R, LB, bb);
 #pragma unroll
@@ -1009,17 +1016,17 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
                 if (hi[a] > V.n[a] - 2) hi[a] = V.n[a] - 2;
                 c[a] = cell_at(R, L1, a, tb0, lo[a], hi[a]);
             }
+            // entry parameter: cell_entry for the first cell; afterwards the
+            // previous cell's exit (the stepped axes' entry planes are the old
+            // exit planes, every other entry plane lies before them)
+            double t0 = cell_entry(R, L1, c);
             Rgbz out;
             out.t = __builtin_inf();
             out.cell = NONE;
             out.rgba = 0u;
             for (int guard = 0; guard < 16; ++guard) {   // at most 10 cells of a 4^3 block lie on a ray
-                double t0 = cell_entry(R, L1, c);
-                double t1 = R.tx;
-                {
-                    double x = cell_exit(R, L1, c);
-                    if (x < t1) t1 = x;
-                }
+                const double tx = cell_exit(R, L1, c);
+                const double t1 = tx < R.tx ? tx : R.tx;
                 float fc[8];
                 int lx = c[0] - lo[0], ly = c[1] - lo[1], lz = c[2] - lo[2];
                 if (staged) {
@@ -1040,8 +1047,8 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
                     out.rgba = shade_hit(R, h, fc);
                     break;
                 }
-                double tn = cell_exit(R, L1, c);
-                if (tn > R.tx || !advance(R, L1, c, tn, lo, hi)) break;
+                if (tx > R.tx || !advance(R, L1, c, tx, lo, hi)) break;
+                t0 = tx;
             }
             q.rgbz[qq] = out;
         }
