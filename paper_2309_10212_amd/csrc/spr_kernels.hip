@@ -88,6 +88,23 @@ __device__ __forceinline__ uint32_t low_bit(uint64_t x) { return (uint32_t)__ffs
 // takes about as many iterations as one block has bits.
 enum : uint32_t { M_REF = 0, M_GT = 1, M_SCAN = 2, M_SIGN = 3, M_DONE = 4 };
 
+// Mode transitions, one nibble per (mode, bit, W exhausted) at index
+// mode*4 + bit*2 + exhausted: low 3 bits the next mode, bit 3 "next plane".
+//   REF:  W left -> REF; W exhausted -> GT (group test from cursor 0)
+//   GT:   bit 0 -> next plane; bit 1 -> SCAN
+//   SCAN: bit 1 -> SIGN; bit 0 with candidates left -> SCAN; none left -> DONE
+//   SIGN: -> GT
+static constexpr uint64_t mode_table() {
+    uint64_t t = 0;
+    const uint32_t e[16] = {M_REF, M_GT, M_REF, M_GT,            // REF
+                            M_GT | 8u, M_GT | 8u, M_SCAN, M_SCAN, // GT
+                            M_SCAN, M_DONE, M_SIGN, M_SIGN,       // SCAN
+                            M_GT, M_GT, M_GT, M_GT};              // SIGN
+    for (int i = 0; i < 16; ++i) t |= (uint64_t)e[i] << (4 * i);
+    return t;
+}
+static constexpr uint64_t kModeTable = mode_table();
+
 template <int RWMAX>
 __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, int rate, DecodeLds<RWMAX> &L,
                                               uint32_t lane, int32_t (&q)[64], int &e_out) {
@@ -115,37 +132,34 @@ __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, 
         buf >>= 1;
         --nbits;
         ++pos;
-        const bool need = nbits < 32u;
-        buf |= need ? ((uint64_t)nxt << nbits) : 0ull;
-        nbits += need ? 32u : 0u;
-        wi += need ? 1u : 0u;
-        nxt = L.rec[wi * 64 + lane];
+        if (nbits < 32u) {   // wave-uniform: every active lane has consumed the same bit count
+            buf |= (uint64_t)nxt << nbits;
+            nbits += 32u;
+            ++wi;
+            nxt = L.rec[wi * 64 + lane];
+        }
 
         const bool isREF = mode == M_REF, isGT = mode == M_GT, isSCAN = mode == M_SCAN, isSIGN = mode == M_SIGN;
         const uint32_t j = (uint32_t)__builtin_ctzll(W | (1ull << 63));   // W != 0 in REF and SCAN
-        if (isREF || isSIGN) {
-            const uint32_t at = isREF ? j : t;
-            const uint32_t v = (isREF ? bit : 1u) << k;
-            __hip_atomic_fetch_or(&L.mag[at * 64 + lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        }
         const uint64_t Wn = W & (W - 1ull);
-        const bool ref_end = isREF && Wn == 0ull;
-        const bool scan_hit = isSCAN && bit;
-        const bool scan_fail = isSCAN && !bit && Wn == 0ull;
+        // refinement bit (REF) or the new coefficient's top bit (SIGN); other
+        // modes OR 0, so every lane issues the same LDS instruction
+        const uint32_t at = isREF ? j : t;
+        const uint32_t v = (isREF ? bit : (isSIGN ? 1u : 0u)) << k;
+        __hip_atomic_fetch_or(&L.mag[at * 64 + lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         const uint64_t tbit = 1ull << t;
         S |= isSIGN ? tbit : 0ull;
         NEG |= (isSIGN && bit) ? tbit : 0ull;
-        c = isSIGN ? t + 1u : (ref_end ? 0u : c);
+        c = isSIGN ? t + 1u : (isREF ? 0u : c);   // REF ends into a group test from cursor 0
         const uint64_t cand = c >= 64u ? 0ull : (~S & (~0ull << c));
-        W = (isREF || isSCAN) ? Wn : ((isGT && bit) ? cand : W);
-        t = scan_hit ? j : t;
-        uint32_t nm = mode;
-        nm = ref_end ? M_GT : nm;
-        nm = (isGT && bit) ? M_SCAN : nm;
-        nm = scan_hit ? M_SIGN : (scan_fail ? M_DONE : nm);
-        nm = isSIGN ? M_GT : nm;
+        t = (isSCAN && bit) ? j : t;
+        // next mode from (mode, bit, W exhausted): nibble = mode | next-plane << 3
+        const uint32_t idx = mode * 4u + bit * 2u + (Wn == 0ull ? 1u : 0u);
+        const uint32_t e = (uint32_t)(kModeTable >> (idx * 4u)) & 15u;
+        uint32_t nm = e & 7u;
         // settle: a group test with no candidate left ends the plane
-        const bool np = (isGT && !bit) || (nm == M_GT && cand == 0ull);
+        const bool np = (e >> 3) != 0u || (nm == M_GT && cand == 0ull);
+        W = isGT ? cand : Wn;   // a group test that hits scans the candidates
         const int kn = np ? k - 1 : k;
         W = np ? S : W;
         c = np ? 0u : c;
