@@ -32,21 +32,31 @@ if ROOT not in sys.path:
 
 METRIC = "rays/s & ms/pass at 1280x720, batched vs plain, same accuracy; blocks decoded/s"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2309_10212_amd/csrc/spr_kernels.hip", "paper_2309_10212_amd/csrc/spr_internal.h",
+                  "paper_2309_10212_amd/csrc/spr_launch.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fourier512_rate4_1280x720.txt")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes per kernel of a pass, in this library's data layout: every
-# input and output byte the kernel must move once (cached re-reads not
-# counted).  Counts are summed over the timed passes:
+# Algorithmic bytes per kernel, in this library's data layout: every input
+# and output byte the kernel must move once (cached re-reads not counted).
+# Counts are summed over the timed region:
 #   A rays, S pair slots (N_act*N_spec), P pairs, Ps served pairs, V visible
-#   blocks, K active blocks, M decoded blocks, R bits/value.
+#   blocks, K active blocks, M decoded blocks, R bits/value; per step (load
+#   path and request set-up): NB blocks, NC coarse cells, NP pixels.
 def kernel_bytes(name, c, rate):
     A, S, P, Ps = c["rays"], c["pair_slots"], c["pairs"], c["served_pairs"]
     V, K, M = c["visible_blocks"], c["active_blocks"], c["blocks_decoded"]
+    NB, NC, NP = c["load_blocks"], c["load_coarse"], c["setup_pixels"]
     model = {
+        "k_block_ranges": (8 * rate + 8) * NB,     # record in, own range out
+        "k_fine_grid": 16 * NB,                    # ranges in, fine range out
+        "k_coarse_grid": 8 * NB + 8 * NC,          # fine ranges in, coarse range out
+        "k_iso_masks": 8 * NC + 8 * NB + 8 * NC,   # coarse + fine ranges in, one mask word out
+        "k_init_rays": 28 * NP,                    # ray state, image, hit record, active entry
         "k_traverse": 8 * A + 4 * S + 8 * V,
         "k_dedupe": 4 * S + 8 * P + 20 * V,
         "k_mark": 4 * S + 16 * P + 8 * V + 16 * K,
@@ -58,6 +68,32 @@ def kernel_bytes(name, c, rate):
         "k_compact": 12 * A,
     }
     return model.get(name)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel calibration), or
+    None if there is none for this kernel or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.strip().split("=", 1) for line in fh if "=" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv[kernel + ".hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def make_inputs(args):
@@ -116,6 +152,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
     ap.add_argument("--batch-reps", type=int, default=3, help="repetitions of the batched orbit (0 = skip)")
     ap.add_argument("--poll-every", type=int, default=2)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the timed region, copy this many MiB device to device once (the plain copy "
+                         "kernel that calibrates the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -153,6 +192,15 @@ def main():
     for i in range(args.warmup):
         step(i, args.spec_cap)
     torch.cuda.synchronize()
+    if args.calib_copy_mib > 0:
+        nbytes = args.calib_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
 
     ctx.profile(not args.no_profile, reset=True)
     c0 = ctx.counters()
@@ -167,15 +215,26 @@ def main():
     c1 = ctx.counters()
     ktimes = ctx.kernel_times()
     dc = {k: c1[k] - c0[k] for k in c1}
+    nb_vol = ((n + 3) // 4) ** 3
+    dc["load_blocks"] = nb_vol * args.steps
+    dc["load_coarse"] = ((((n + 3) // 4) + 3) // 4) ** 3 * args.steps
+    dc["setup_pixels"] = args.w * args.h * args.steps
     elapsed = t1 - t0
     rays = sum(i["rays_entered"] for i in infos)
     passes = sum(i["passes"] for i in infos)
     value = rays / elapsed
-    dev_ms = sum(ms for ms, _ in ktimes.values())
+    PASS_KERNELS = ("k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_alloc_plan", "k_evict_hist",
+                    "k_evict", "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact")
+    dev_ms_all = sum(ms for ms, _ in ktimes.values())
+    # pass kernels only (the set-up pass also runs k_pass_begin/k_pass_end/k_compact once per step)
+    dev_ms = sum(ktimes[k][0] for k in PASS_KERNELS if k in ktimes)
     dec_ms = ktimes.get("k_decode", (0.0, 0))[0]
 
-    # roofline of the dominant kernel (largest device time in the timed region)
+    # roofline of the dominant kernel (largest device time in the timed
+    # region: the load path, request set-up and every pass)
     dom = max(ktimes.items(), key=lambda kv: kv[1][0])
+    log("[bench] device ms per step by kernel: " + ", ".join(
+        f"{k} {ms / args.steps:.3f} ({nl})" for k, (ms, nl) in sorted(ktimes.items(), key=lambda kv: -kv[1][0])[:8]))
     dname, (dms, dn) = dom
     byts = kernel_bytes(dname, dc, args.rate)
     roof = None
@@ -184,7 +243,7 @@ def main():
         avg_s = dms / dn / 1e3
         ach = per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 6), "traffic": None, "kernel": dname,
+                "frac": round(ach / HBM_PEAK_GBS, 6), "traffic": measured_traffic(dname), "kernel": dname,
                 "bytes_per_launch": round(per_launch), "avg_launch_us": round(avg_s * 1e6, 2)}
 
     # speculation sweep over the whole orbit (outside the timed region)
@@ -260,6 +319,7 @@ def main():
                    "step": "grid rebuild + initial rays + passes to completion, one orbit view"},
         "ms_per_pass": round(elapsed * 1e3 / max(passes, 1), 4),
         "device_ms_per_pass": round(dev_ms / max(passes, 1), 4),
+        "device_ms_per_step": round(dev_ms_all / max(args.steps, 1), 4),
         "passes_per_step": passes / args.steps,
         "blocks_decoded_per_s": round(dc["blocks_decoded"] / elapsed, 1),
         "blocks_decoded_per_decode_s": round(dc["blocks_decoded"] / (dec_ms / 1e3), 1) if dec_ms > 0 else None,

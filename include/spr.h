@@ -161,7 +161,10 @@ spr_status spr_mem_stats(spr_ctx *ctx, size_t *current, size_t *peak);
 spr_status spr_ctx_counters(spr_ctx *ctx, spr_counters *out);
 /* Profiling mode: when enabled, passes run eagerly (not from a captured
  * graph) with a HIP event recorded on the context stream before and after
- * every kernel; per-kernel device times accumulate until reset. */
+ * every kernel, also around the load-path kernels of spr_volume_build_grids
+ * and the set-up kernels of spr_render_begin; the events are read back
+ * lazily (no host synchronisation per pass) and per-kernel device times
+ * accumulate until reset. */
 spr_status spr_ctx_profile(spr_ctx *ctx, int enable, int reset);
 /* Copy up to max per-kernel totals (synchronises); *n = kernels reported. */
 spr_status spr_ctx_kernel_times(spr_ctx *ctx, spr_kernel_time *out, uint32_t max, uint32_t *n);

@@ -64,9 +64,20 @@ struct spr_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only to record graphs
     bool prof = false;
-    hipEvent_t prof_ev[PASS_KERNELS + 1] = {};
-    double prof_ms[PASS_KERNELS] = {};
-    uint64_t prof_n[PASS_KERNELS] = {};
+    // Profiling: a ring of event sets, read back only when a set is reused
+    // or the totals are requested, so profiled passes need no host sync.
+    static constexpr int PROF_RING = 64;
+    struct ProfRec {
+        hipEvent_t ev[PASS_KERNELS + 1] = {};
+        const int *slots = nullptr;
+        int nk = 0;
+        bool pending = false;
+    };
+    ProfRec prof_ring[PROF_RING];
+    uint32_t prof_head = 0;
+    bool prof_events = false;
+    double prof_ms[PROF_SLOTS] = {};
+    uint64_t prof_n[PROF_SLOTS] = {};
     void *pinned = nullptr;     // small host staging area
     int n_renders = 0;
 };
@@ -289,20 +300,46 @@ spr_status graph_pass(spr_ctx *c, const Table &T, const PassGrids &g, hipGraph_t
     return SPR_OK;
 }
 
+// Profiling: add one recorded event set's kernel intervals to their slots.
+constexpr int PASS_SLOTS[PASS_KERNELS] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13};
+
+spr_status prof_collect(spr_ctx *c, spr_ctx::ProfRec &rec) {
+    if (!rec.pending) return SPR_OK;
+    rec.pending = false;
+    HIPCHK(hipEventSynchronize(rec.ev[rec.nk]));
+    for (int k = 0; k < rec.nk; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, rec.ev[k], rec.ev[k + 1]));
+        c->prof_ms[rec.slots[k]] += ms;
+        c->prof_n[rec.slots[k]] += 1;
+    }
+    return SPR_OK;
+}
+
+// The next event set for nk kernels (collecting the set it replaces first).
+spr_status prof_begin(spr_ctx *c, int nk, const int *slots, hipEvent_t **ev) {
+    spr_ctx::ProfRec &rec = c->prof_ring[c->prof_head];
+    CHK(prof_collect(c, rec));
+    rec.nk = nk;
+    rec.slots = slots;
+    rec.pending = true;
+    c->prof_head = (c->prof_head + 1) % spr_ctx::PROF_RING;
+    *ev = rec.ev;
+    return SPR_OK;
+}
+
+// Collect every pending set, oldest first.
+spr_status prof_flush(spr_ctx *c) {
+    for (int i = 0; i < spr_ctx::PROF_RING; ++i)
+        CHK(prof_collect(c, c->prof_ring[(c->prof_head + i) % spr_ctx::PROF_RING]));
+    return SPR_OK;
+}
+
 // One pass of a launch table, eager; in profiling mode with per-kernel events.
 spr_status run_pass(spr_ctx *c, const Table &T, const PassGrids &g) {
-    if (!c->prof) {
-        HIPCHK(launch_pass(c->stream, c->ctl, T, c->d_vols, c->work, c->cache, g, nullptr));
-        return SPR_OK;
-    }
-    HIPCHK(launch_pass(c->stream, c->ctl, T, c->d_vols, c->work, c->cache, g, c->prof_ev));
-    HIPCHK(hipEventSynchronize(c->prof_ev[PASS_KERNELS]));
-    for (int k = 0; k < PASS_KERNELS; ++k) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, c->prof_ev[k], c->prof_ev[k + 1]));
-        c->prof_ms[k] += ms;
-        c->prof_n[k] += 1;
-    }
+    hipEvent_t *ev = nullptr;
+    if (c->prof) CHK(prof_begin(c, PASS_KERNELS, PASS_SLOTS, &ev));
+    HIPCHK(launch_pass(c->stream, c->ctl, T, c->d_vols, c->work, c->cache, g, ev));
     return SPR_OK;
 }
 
@@ -354,7 +391,7 @@ spr_status spr_ctx_create(const spr_config *cfg, spr_ctx **out) {
         return fail(SPR_E_OOM, "pinned host allocation failed");
     }
     bool evok = true;
-    for (auto &e : c->prof_ev) evok = evok && hipEventCreate(&e) == hipSuccess;
+
     if (!evok || hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         spr_ctx_destroy(c);
@@ -398,8 +435,9 @@ spr_status spr_ctx_destroy(spr_ctx *c) {
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    for (auto &e : c->prof_ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto &rec : c->prof_ring)
+        for (auto &e : rec.ev)
+            if (e) (void)hipEventDestroy(e);
     delete c;
     return SPR_OK;
 }
@@ -432,9 +470,16 @@ spr_status spr_ctx_counters(spr_ctx *c, spr_counters *o) {
 
 spr_status spr_ctx_profile(spr_ctx *c, int enable, int reset) {
     if (!c) return fail(SPR_E_INVALID, "null context");
+    HIPCHK(hipSetDevice(c->device));
+    if (enable && !c->prof_events) {
+        for (auto &rec : c->prof_ring)
+            for (auto &e : rec.ev) HIPCHK(hipEventCreate(&e));
+        c->prof_events = true;
+    }
+    CHK(prof_flush(c));
     c->prof = enable != 0;
     if (reset) {
-        for (int k = 0; k < PASS_KERNELS; ++k) { c->prof_ms[k] = 0; c->prof_n[k] = 0; }
+        for (int k = 0; k < PROF_SLOTS; ++k) { c->prof_ms[k] = 0; c->prof_n[k] = 0; }
     }
     return SPR_OK;
 }
@@ -443,9 +488,10 @@ spr_status spr_ctx_kernel_times(spr_ctx *c, spr_kernel_time *out, uint32_t max, 
     if (!c || !n || (!out && max)) return fail(SPR_E_INVALID, "null argument");
     HIPCHK(hipSetDevice(c->device));
     HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(prof_flush(c));
     uint32_t k = 0;
-    for (; k < (uint32_t)PASS_KERNELS && k < max; ++k) {
-        out[k].name = PASS_KERNEL_NAMES[k];
+    for (; k < (uint32_t)PROF_SLOTS && k < max; ++k) {
+        out[k].name = PROF_NAMES[k];
         out[k].total_ms = c->prof_ms[k];
         out[k].launches = c->prof_n[k];
     }
@@ -566,7 +612,9 @@ spr_status spr_volume_build_grids(spr_volume *v) {
     if (!v) return fail(SPR_E_INVALID, "null volume");
     spr_ctx *c = v->ctx;
     HIPCHK(hipSetDevice(c->device));
-    HIPCHK(launch_load_grids(c->stream, c->h_vols[v->idx]));
+    hipEvent_t *ev = nullptr;
+    if (c->prof) CHK(prof_begin(c, 3, LOAD_SLOTS, &ev));
+    HIPCHK(launch_load_grids(c->stream, c->h_vols[v->idx], ev));
     return SPR_OK;
 }
 
@@ -703,7 +751,9 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     hipError_t e = hipMemcpy(r->d_st, &s0, sizeof(s0), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r->table.hdr, &one, sizeof(one), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r->d_req, &q, sizeof(q), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols, r->cwords);
+    hipEvent_t *pev = nullptr;
+    if (e == hipSuccess && c->prof && prof_begin(c, 5, INIT_SLOTS, &pev) != SPR_OK) e = hipErrorUnknown;
+    if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols, r->cwords, pev);
     if (e != hipSuccess) {
         free_render_buffers(c, r);
         delete r;

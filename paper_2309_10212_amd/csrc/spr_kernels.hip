@@ -1305,15 +1305,22 @@ hipError_t launch_fp64_ops(hipStream_t s, const double *x, const double *y, uint
     return hipGetLastError();
 }
 
-hipError_t launch_load_grids(hipStream_t s, const VolDev &V) {
+hipError_t launch_load_grids(hipStream_t s, const VolDev &V, hipEvent_t *ev) {
+    int k = 0;
+    auto mark = [&]() {
+        if (ev) (void)hipEventRecord(ev[k], s);
+        ++k;
+    };
     dim3 g(grid_for(V.nblocks, 64, 1u << 16)), b(64);
+    mark();
     if (V.rec_words <= 4) hipLaunchKernelGGL(k_block_ranges<4>, g, b, 0, s, V, V.blk);
     else if (V.rec_words <= 8) hipLaunchKernelGGL(k_block_ranges<8>, g, b, 0, s, V, V.blk);
     else if (V.rec_words <= 16) hipLaunchKernelGGL(k_block_ranges<16>, g, b, 0, s, V, V.blk);
     else hipLaunchKernelGGL(k_block_ranges<32>, g, b, 0, s, V, V.blk);
-    hipLaunchKernelGGL(k_fine_grid, dim3(grid_for(V.nblocks, 256, 1u << 16)), dim3(256), 0, s, V);
+    mark(); hipLaunchKernelGGL(k_fine_grid, dim3(grid_for(V.nblocks, 256, 1u << 16)), dim3(256), 0, s, V);
     uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
-    hipLaunchKernelGGL(k_coarse_grid, dim3(grid_for(nc, 256, 1u << 16)), dim3(256), 0, s, V);
+    mark(); hipLaunchKernelGGL(k_coarse_grid, dim3(grid_for(nc, 256, 1u << 16)), dim3(256), 0, s, V);
+    mark();
     return hipGetLastError();
 }
 
@@ -1337,18 +1344,30 @@ hipError_t launch_release_volume(hipStream_t s, PassCtl *ctl, const Cache &C, ui
     return hipGetLastError();
 }
 
-hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words) {
-    hipLaunchKernelGGL(k_iso_masks, dim3(grid_for(mask_words, 256, 8192)), dim3(256), 0, s, T, vols);
-    hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, ctl, T, 1);
-    hipLaunchKernelGGL(k_init_rays, dim3(grid_for(T.max_A, 256, 16384)), dim3(256), 0, s, ctl, T, vols);
-    hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, s, ctl, T, 1);
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(T.max_A, 256, 16384)), dim3(256), 0, s, ctl, T);
+hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words,
+                            hipEvent_t *ev) {
+    int k = 0;
+    auto mark = [&]() {
+        if (ev) (void)hipEventRecord(ev[k], s);
+        ++k;
+    };
+    mark(); hipLaunchKernelGGL(k_iso_masks, dim3(grid_for(mask_words, 256, 8192)), dim3(256), 0, s, T, vols);
+    mark(); hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, ctl, T, 1);
+    mark(); hipLaunchKernelGGL(k_init_rays, dim3(grid_for(T.max_A, 256, 16384)), dim3(256), 0, s, ctl, T, vols);
+    mark(); hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, s, ctl, T, 1);
+    mark(); hipLaunchKernelGGL(k_compact, dim3(grid_for(T.max_A, 256, 16384)), dim3(256), 0, s, ctl, T);
+    mark();
     return hipGetLastError();
 }
 
 const char *const PASS_KERNEL_NAMES[PASS_KERNELS] = {
     "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_alloc_plan", "k_evict_hist", "k_evict",
     "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact"};
+
+const char *const PROF_NAMES[PROF_SLOTS] = {
+    "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_alloc_plan", "k_evict_hist", "k_evict",
+    "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact",
+    "k_block_ranges", "k_fine_grid", "k_coarse_grid", "k_iso_masks", "k_init_rays"};
 
 hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, const Work &W,
                        const Cache &C, const PassGrids &g, hipEvent_t *ev) {

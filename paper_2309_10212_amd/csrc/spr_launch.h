@@ -21,15 +21,26 @@ struct PassGrids {
 
 hipError_t launch_decode_ids(hipStream_t s, const VolDev &V, const uint32_t *ids, uint32_t n, float *out);
 hipError_t launch_fp64_ops(hipStream_t s, const double *x, const double *y, uint64_t n, double *sq, double *dv);
-hipError_t launch_load_grids(hipStream_t s, const VolDev &V);
+// Load path: block ranges, fine grid, coarse grid.  ev == nullptr: plain
+// launches; else ev[i] is recorded before kernel i and ev[3] after the last.
+hipError_t launch_load_grids(hipStream_t s, const VolDev &V, hipEvent_t *ev = nullptr);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t v);
 hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n, uint64_t v);
 hipError_t launch_iota_u32(hipStream_t s, uint32_t *p, uint64_t n);
 hipError_t launch_release_volume(hipStream_t s, PassCtl *ctl, const Cache &C, uint32_t vol);
-// Isovalue masks of the table's first request, then the initial-ray pass.
-hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words);
+// Isovalue masks of the table's first request, then the initial-ray pass
+// (masks, pass set-up, initial rays, count, compaction); ev as for the load
+// path, with ev[5] after the last kernel.
+hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words,
+                            hipEvent_t *ev = nullptr);
 constexpr int PASS_KERNELS = 14;
 extern const char *const PASS_KERNEL_NAMES[PASS_KERNELS];
+// Profiling slots: the pass kernels, then the load-path and set-up kernels
+// that run outside a pass.
+constexpr int PROF_SLOTS = PASS_KERNELS + 5;
+extern const char *const PROF_NAMES[PROF_SLOTS];
+constexpr int LOAD_SLOTS[3] = {14, 15, 16};           // block ranges, fine grid, coarse grid
+constexpr int INIT_SLOTS[5] = {17, 0, 18, 12, 13};    // masks, pass begin, initial rays, pass end, compact
 // ev == nullptr: plain launches; else ev[i] is recorded before kernel i and
 // ev[PASS_KERNELS] after the last one.
 hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, const Work &W,
