@@ -55,12 +55,12 @@ def kernel_bytes(name, c, rate):
         "k_block_ranges": (8 * rate + 8) * NB,     # record in, own range out
         "k_fine_grid": 16 * NB,                    # ranges in, fine range out
         "k_coarse_grid": 8 * NB + 8 * NC,          # fine ranges in, coarse range out
-        "k_iso_masks": 8 * NC + 8 * NB + 8 * NC,   # coarse + fine ranges in, one mask word out
+        "k_iso_masks": 8 * NB + 16 * NC,           # coarse + fine ranges in, one mask word out
         "k_init_rays": 28 * NP,                    # ray state, image, hit record, active entry
         "k_traverse": 8 * A + 4 * S + 8 * V,
-        "k_dedupe": 4 * S + 8 * P + 20 * V,
-        "k_mark": 4 * S + 16 * P + 8 * V + 16 * K,
-        "k_lookup": 8 * V + 24 * K + 8 * M,
+        "k_dedupe": 4 * S + 12 * P + 12 * V,
+        "k_mark": 20 * V + 16 * K,
+        "k_lookup": 16 * K + 8 * M,
         "k_assign_scatter": 32 * M + 4 * S + 28 * Ps,
         "k_decode": (8 * rate + 268) * M,
         "k_raytrace": 36 * Ps + 532 * V,
