@@ -63,6 +63,10 @@ def _load():
         lib.orc_schedule_lists.argtypes = [ctypes.c_uint64, ctypes.c_size_t, P, P, P, P, ctypes.c_long,
                                            ctypes.c_long, ctypes.c_long, ctypes.c_uint32, ctypes.c_long, P]
         lib.orc_schedule_lists.restype = ctypes.c_long
+        lib.orc_render_stream.argtypes = [P, ctypes.c_size_t, i, i, i, i, ctypes.POINTER(_Cam), ctypes.c_float,
+                                          i, i, P, ctypes.c_size_t, P, P, P, P, P]
+        lib.orc_block_ranges_stream.argtypes = [P, ctypes.c_size_t, i, i, i, i, P]
+        lib.orc_grids_from_blocks.argtypes = [P, i, i, i, P, P]
         lib.orc_blocks_containing.argtypes = [P, ctypes.c_size_t, ctypes.c_float]
         lib.orc_blocks_containing.restype = ctypes.c_uint64
         _lib = lib
@@ -161,6 +165,53 @@ def render(vol: np.ndarray, cam, iso: float, w: int, h: int, pixels=None):
                            _p(pix) if pix is not None else None, n, _p(t), _p(b), _p(c), _p(rgba), _p(ent)),
         "render")
     return {"t": t, "block": b, "cell": c, "rgba": rgba, "entered": ent.astype(bool)}
+
+
+def render_stream(stream: np.ndarray, dims, rate: int, cam, iso: float, w: int, h: int, pixels=None):
+    """render() for a volume given as its compressed stream: the same march, with
+    each corner read from its block decoded on demand (volumes too large to
+    decode whole; sampled pixels)."""
+    nx, ny, nz = dims
+    s = np.ascontiguousarray(stream, np.uint8)
+    if pixels is None:
+        n = w * h
+        pix = None
+    else:
+        pix = np.ascontiguousarray(pixels, np.uint32)
+        n = len(pix)
+    t = np.empty(n, np.float64)
+    b = np.empty(n, np.uint32)
+    c = np.empty(n, np.uint32)
+    rgba = np.empty(n, np.uint32)
+    ent = np.empty(n, np.uint8)
+    cc = _cam(cam)
+    _ok(_load().orc_render_stream(_p(s), s.nbytes, nx, ny, nz, rate, ctypes.byref(cc), ctypes.c_float(iso), w, h,
+                                  _p(pix) if pix is not None else None, n, _p(t), _p(b), _p(c), _p(rgba), _p(ent)),
+        "render_stream")
+    return {"t": t, "block": b, "cell": c, "rgba": rgba, "entered": ent.astype(bool)}
+
+
+def block_ranges_stream(stream: np.ndarray, dims, rate: int) -> np.ndarray:
+    """Per-block (min, max) over the samples inside the volume, decoding one
+    block at a time from the stream (the block ranges of grids())."""
+    nx, ny, nz = dims
+    s = np.ascontiguousarray(stream, np.uint8)
+    nb = ((nx + 3) // 4) * ((ny + 3) // 4) * ((nz + 3) // 4)
+    out = np.empty((nb, 2), np.float32)
+    _ok(_load().orc_block_ranges_stream(_p(s), s.nbytes, nx, ny, nz, rate, _p(out)), "block_ranges_stream")
+    return out
+
+
+def grids_from_blocks(block: np.ndarray, dims):
+    """(fine, coarse) ranges from block ranges, as grids() builds them."""
+    nx, ny, nz = dims
+    blk = np.ascontiguousarray(block, np.float32)
+    nbx, nby, nbz = (nx + 3) // 4, (ny + 3) // 4, (nz + 3) // 4
+    nc = ((nbx + 3) // 4) * ((nby + 3) // 4) * ((nbz + 3) // 4)
+    fine = np.empty((nbx * nby * nbz, 2), np.float32)
+    coarse = np.empty((nc, 2), np.float32)
+    _ok(_load().orc_grids_from_blocks(_p(blk), nx, ny, nz, _p(fine), _p(coarse)), "grids_from_blocks")
+    return fine, coarse
 
 
 def cell_walk(dims, cam, w: int, h: int, px: int, py: int, cap: int = 1 << 16):

@@ -175,6 +175,47 @@ int orc_decode_volume(const void *stream, size_t bytes, int nx, int ny, int nz, 
  * coarse_lohi[2*c]  : union of fine ranges over blocks 4c .. 4c+3 that exist
  * (Sec. 3.1: a cell's range is its own range combined with its +x/+y/+z
  * neighbours, so the dual grid's values are covered).  Any output may be NULL. */
+/* fine and coarse ranges from the block ranges (any output may be NULL) */
+static void grids_from_blocks(const float *blk, long nbx, long nby, long nbz, float *fin, float *coarse_lohi) {
+    if (fin) {
+#pragma omp parallel for schedule(static)
+        for (long bz = 0; bz < nbz; ++bz)
+            for (long by = 0; by < nby; ++by)
+                for (long bx = 0; bx < nbx; ++bx) {
+                    float lo = INFINITY, hi = -INFINITY;
+                    for (int dz = 0; dz < 2; ++dz)
+                        for (int dy = 0; dy < 2; ++dy)
+                            for (int dx = 0; dx < 2; ++dx) {
+                                long x = bx + dx, y = by + dy, z = bz + dz;
+                                if (x >= nbx || y >= nby || z >= nbz) continue;
+                                size_t o = (size_t)((z * nby + y) * nbx + x);
+                                if (blk[2 * o] < lo) lo = blk[2 * o];
+                                if (blk[2 * o + 1] > hi) hi = blk[2 * o + 1];
+                            }
+                    size_t b = (size_t)((bz * nby + by) * nbx + bx);
+                    fin[2 * b] = lo; fin[2 * b + 1] = hi;
+                }
+    }
+    if (coarse_lohi && fin) {
+        long ncx = (nbx + 3) / 4, ncy = (nby + 3) / 4, ncz = (nbz + 3) / 4;
+#pragma omp parallel for schedule(static)
+        for (long cz = 0; cz < ncz; ++cz)
+            for (long cy = 0; cy < ncy; ++cy)
+                for (long cx = 0; cx < ncx; ++cx) {
+                    float lo = INFINITY, hi = -INFINITY;
+                    for (long z = 4 * cz; z < 4 * cz + 4 && z < nbz; ++z)
+                        for (long y = 4 * cy; y < 4 * cy + 4 && y < nby; ++y)
+                            for (long x = 4 * cx; x < 4 * cx + 4 && x < nbx; ++x) {
+                                size_t o = (size_t)((z * nby + y) * nbx + x);
+                                if (fin[2 * o] < lo) lo = fin[2 * o];
+                                if (fin[2 * o + 1] > hi) hi = fin[2 * o + 1];
+                            }
+                    size_t c = (size_t)((cz * ncy + cy) * ncx + cx);
+                    coarse_lohi[2 * c] = lo; coarse_lohi[2 * c + 1] = hi;
+                }
+    }
+}
+
 int orc_grids(const float *vol, int nx, int ny, int nz, float *block_lohi, float *fine_lohi,
               float *coarse_lohi) {
     if (!vol || nx < 1 || ny < 1 || nz < 1) return ORC_EINVAL;
@@ -197,42 +238,51 @@ int orc_grids(const float *vol, int nx, int ny, int nz, float *block_lohi, float
                 size_t b = (size_t)((bz * nby + by) * nbx + bx);
                 blk[2 * b] = lo; blk[2 * b + 1] = hi;
             }
-    for (long bz = 0; bz < nbz; ++bz)
-        for (long by = 0; by < nby; ++by)
-            for (long bx = 0; bx < nbx; ++bx) {
-                float lo = INFINITY, hi = -INFINITY;
-                for (int dz = 0; dz < 2; ++dz)
-                    for (int dy = 0; dy < 2; ++dy)
-                        for (int dx = 0; dx < 2; ++dx) {
-                            long x = bx + dx, y = by + dy, z = bz + dz;
-                            if (x >= nbx || y >= nby || z >= nbz) continue;
-                            size_t o = (size_t)((z * nby + y) * nbx + x);
-                            if (blk[2 * o] < lo) lo = blk[2 * o];
-                            if (blk[2 * o + 1] > hi) hi = blk[2 * o + 1];
-                        }
-                size_t b = (size_t)((bz * nby + by) * nbx + bx);
-                fin[2 * b] = lo; fin[2 * b + 1] = hi;
-            }
-    if (coarse_lohi) {
-        long ncx = (nbx + 3) / 4, ncy = (nby + 3) / 4, ncz = (nbz + 3) / 4;
-        for (long cz = 0; cz < ncz; ++cz)
-            for (long cy = 0; cy < ncy; ++cy)
-                for (long cx = 0; cx < ncx; ++cx) {
-                    float lo = INFINITY, hi = -INFINITY;
-                    for (long z = 4 * cz; z < 4 * cz + 4 && z < nbz; ++z)
-                        for (long y = 4 * cy; y < 4 * cy + 4 && y < nby; ++y)
-                            for (long x = 4 * cx; x < 4 * cx + 4 && x < nbx; ++x) {
-                                size_t o = (size_t)((z * nby + y) * nbx + x);
-                                if (fin[2 * o] < lo) lo = fin[2 * o];
-                                if (fin[2 * o + 1] > hi) hi = fin[2 * o + 1];
-                            }
-                    size_t c = (size_t)((cz * ncy + cy) * ncx + cx);
-                    coarse_lohi[2 * c] = lo; coarse_lohi[2 * c + 1] = hi;
-                }
-    }
+    grids_from_blocks(blk, nbx, nby, nbz, fin, coarse_lohi);
     if (block_lohi) memcpy(block_lohi, blk, sizeof(float) * 2 * nb);
     if (fine_lohi) memcpy(fine_lohi, fin, sizeof(float) * 2 * nb);
     free(blk); free(fin);
+    return ORC_OK;
+}
+
+/* Block ranges straight from the compressed stream, one block decoded at a
+ * time (no whole-volume buffer): min/max over each block's samples inside
+ * the volume, the block_lohi of orc_grids. */
+int orc_block_ranges_stream(const void *stream, size_t bytes, int nx, int ny, int nz, int R, float *block_lohi) {
+    if (!stream || !block_lohi || nx < 1 || ny < 1 || nz < 1) return ORC_EINVAL;
+    if (!((R >= 1 && R <= 16) || R == 32)) return ORC_EINVAL;
+    long nbx = nblk_axis(nx), nby = nblk_axis(ny), nbz = nblk_axis(nz);
+    if (bytes != (size_t)nbx * nby * nbz * 8u * (size_t)R) return ORC_EINVAL;
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (long b = 0; b < nbx * nby * nbz; ++b) {
+        float v[64];
+        orc_decode_block((const uint32_t *)stream + (size_t)b * 2u * (size_t)R, R, v);
+        long bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+        float lo = INFINITY, hi = -INFINITY;
+        for (int k = 0; k < 4 && 4 * bz + k < nz; ++k)
+            for (int j = 0; j < 4 && 4 * by + j < ny; ++j)
+                for (int i = 0; i < 4 && 4 * bx + i < nx; ++i) {
+                    float x = v[i + 4 * j + 16 * k];
+                    if (x < lo) lo = x;
+                    if (x > hi) hi = x;
+                }
+        block_lohi[2 * b] = lo; block_lohi[2 * b + 1] = hi;
+    }
+    return ORC_OK;
+}
+
+/* Fine and coarse ranges from given block ranges (as orc_grids computes them
+ * from the decoded volume).  Either output may be NULL. */
+int orc_grids_from_blocks(const float *block_lohi, int nx, int ny, int nz, float *fine_lohi, float *coarse_lohi) {
+    if (!block_lohi || nx < 1 || ny < 1 || nz < 1) return ORC_EINVAL;
+    long nbx = nblk_axis(nx), nby = nblk_axis(ny), nbz = nblk_axis(nz);
+    float *fin = fine_lohi;
+    if (!fin) {
+        fin = (float *)malloc(sizeof(float) * 2 * (size_t)nbx * nby * nbz);
+        if (!fin) return ORC_ENOMEM;
+    }
+    grids_from_blocks(block_lohi, nbx, nby, nbz, fin, coarse_lohi);
+    if (fin != fine_lohi) free(fin);
     return ORC_OK;
 }
 
@@ -416,17 +466,11 @@ typedef struct {
     double c[8];                    /* corner values, a fastest */
 } cell_result;
 
-/* Test the dual cell c along [t0, t1].  corner (a,b,g) value = vol at
- * (c0+a, c1+b, c2+g), index a + 2b + 4g. */
-static void test_cell(const float *vol, const ray_t *ray, const long c[3], double t0, double t1,
+/* Test the dual cell c along [t0, t1]; fc[a + 2b + 4g] is the sample at
+ * (c0+a, c1+b, c2+g). */
+static void test_cell(const float fc[8], const ray_t *ray, const long c[3], double t0, double t1,
                       float iso, cell_result *res) {
     res->hit = 0;
-    long nx = ray->n[0], ny = ray->n[1];
-    float fc[8];
-    for (int g = 0; g < 2; ++g)
-        for (int b = 0; b < 2; ++b)
-            for (int a = 0; a < 2; ++a)
-                fc[a + 2 * b + 4 * g] = vol[((c[2] + g) * ny + (c[1] + b)) * nx + (c[0] + a)];
     int above = 0, below = 0;
     for (int i = 0; i < 8; ++i) {
         if (fc[i] > iso) above++;
@@ -528,7 +572,57 @@ typedef struct {
     int entered;
 } pixel_result;
 
-static void trace_pixel(const float *vol, int nx, int ny, int nz, const cam_basis *cb, float iso,
+/* Where a march reads a dual cell's 8 corner samples: the whole decoded
+ * volume, or blocks decoded on demand from the compressed stream (for
+ * volumes too large to decode whole). */
+typedef struct corner_src {
+    void (*fetch)(struct corner_src *src, const long c[3], float fc[8]);
+} corner_src;
+
+typedef struct {
+    corner_src base;
+    const float *vol;
+    long nx, ny;
+} flat_src;
+
+static void flat_fetch(corner_src *src, const long c[3], float fc[8]) {
+    const flat_src *f = (const flat_src *)src;
+    for (int g = 0; g < 2; ++g)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a)
+                fc[a + 2 * b + 4 * g] = f->vol[((c[2] + g) * f->ny + (c[1] + b)) * f->nx + (c[0] + a)];
+}
+
+#define LAZY_SLOTS 64
+typedef struct {
+    corner_src base;
+    const uint32_t *stream;
+    int R;
+    long nbx, nby;
+    size_t rec_words;
+    long tag[LAZY_SLOTS];            /* block id held by each slot, -1 = empty */
+    float val[LAZY_SLOTS][64];
+} lazy_src;
+
+/* sample (x, y, z): its block decoded into a direct-mapped slot on first use */
+static float lazy_sample(lazy_src *L, long x, long y, long z) {
+    long b = (x >> 2) + L->nbx * ((y >> 2) + L->nby * (z >> 2));
+    int s = (int)(b % LAZY_SLOTS);
+    if (L->tag[s] != b) {
+        orc_decode_block(L->stream + (size_t)b * L->rec_words, L->R, L->val[s]);
+        L->tag[s] = b;
+    }
+    return L->val[s][(x & 3) + 4 * (y & 3) + 16 * (z & 3)];
+}
+
+static void lazy_fetch(corner_src *src, const long c[3], float fc[8]) {
+    lazy_src *L = (lazy_src *)src;
+    for (int g = 0; g < 2; ++g)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) fc[a + 2 * b + 4 * g] = lazy_sample(L, c[0] + a, c[1] + b, c[2] + g);
+}
+
+static void trace_pixel(corner_src *src, int nx, int ny, int nz, const cam_basis *cb, float iso,
                         int px, int py, pixel_result *out) {
     ray_t ray;
     make_ray(cb, nx, ny, nz, px, py, &ray);
@@ -542,7 +636,9 @@ static void trace_pixel(const float *vol, int nx, int ny, int nz, const cam_basi
         double t0, t1;
         cell_interval(&ray, c, &t0, &t1);
         cell_result r;
-        test_cell(vol, &ray, c, t0, t1, iso, &r);
+        float fc[8];
+        src->fetch(src, c, fc);
+        test_cell(fc, &ray, c, t0, t1, iso, &r);
         if (r.hit) {
             out->t = t0 + r.s;
             out->block = (uint32_t)((c[0] >> 2) + nbx * ((c[1] >> 2) + nby * (c[2] >> 2)));
@@ -569,12 +665,57 @@ int orc_render(const float *vol, int nx, int ny, int nz, const orc_camera *cam, 
     for (long i = 0; i < (long)n; ++i) {
         uint32_t p = pix ? pix[i] : (uint32_t)i;
         pixel_result r;
-        trace_pixel(vol, nx, ny, nz, &cb, iso, (int)(p % (uint32_t)w), (int)(p / (uint32_t)w), &r);
+        flat_src src = {{flat_fetch}, vol, nx, ny};
+        trace_pixel(&src.base, nx, ny, nz, &cb, iso, (int)(p % (uint32_t)w), (int)(p / (uint32_t)w), &r);
         if (t_out) t_out[i] = r.t;
         if (block_out) block_out[i] = r.block;
         if (cell_out) cell_out[i] = r.cell;
         if (rgba_out) rgba_out[i] = r.rgba;
         if (entered_out) entered_out[i] = (uint8_t)r.entered;
+    }
+    return ORC_OK;
+}
+
+/* orc_render for a volume given only as its compressed stream (format of
+ * orc_decode_block): the same march, reading each corner from its block
+ * decoded on demand.  For sampled parity on volumes too large to decode
+ * whole; results equal orc_render on the decoded volume. */
+int orc_render_stream(const void *stream, size_t bytes, int nx, int ny, int nz, int R, const orc_camera *cam,
+                      float iso, int w, int h, const uint32_t *pix, size_t npix, double *t_out,
+                      uint32_t *block_out, uint32_t *cell_out, uint32_t *rgba_out, uint8_t *entered_out) {
+    if (!stream || !cam || w < 1 || h < 1 || nx < 2 || ny < 2 || nz < 2) return ORC_EINVAL;
+    if (!((R >= 1 && R <= 16) || R == 32)) return ORC_EINVAL;
+    long nbx = nblk_axis(nx), nby = nblk_axis(ny), nbz = nblk_axis(nz);
+    if (bytes != (size_t)nbx * nby * nbz * 8u * (size_t)R) return ORC_EINVAL;
+    cam_basis cb;
+    if (make_basis(cam, w, h, &cb)) return ORC_EINVAL;
+    size_t n = pix ? npix : (size_t)w * h;
+    if (pix)
+        for (size_t i = 0; i < n; ++i)
+            if (pix[i] >= (uint32_t)w * (uint32_t)h) return ORC_EINVAL;
+#pragma omp parallel
+    {
+        lazy_src *L = (lazy_src *)malloc(sizeof(lazy_src));
+        if (L) {
+            L->base.fetch = lazy_fetch;
+            L->stream = (const uint32_t *)stream;
+            L->R = R;
+            L->nbx = nbx; L->nby = nby;
+            L->rec_words = 2u * (size_t)R;
+            for (int k = 0; k < LAZY_SLOTS; ++k) L->tag[k] = -1;
+        }
+#pragma omp for schedule(dynamic, 4)
+        for (long i = 0; i < (long)n; ++i) {
+            uint32_t p = pix ? pix[i] : (uint32_t)i;
+            pixel_result r = {INFINITY, ORC_NONE, ORC_NONE, 0, 0};
+            if (L) trace_pixel(&L->base, nx, ny, nz, &cb, iso, (int)(p % (uint32_t)w), (int)(p / (uint32_t)w), &r);
+            if (t_out) t_out[i] = L ? r.t : NAN;
+            if (block_out) block_out[i] = r.block;
+            if (cell_out) cell_out[i] = r.cell;
+            if (rgba_out) rgba_out[i] = r.rgba;
+            if (entered_out) entered_out[i] = (uint8_t)r.entered;
+        }
+        free(L);
     }
     return ORC_OK;
 }
@@ -663,7 +804,10 @@ static long ray_candidates(const float *vol, const float *fine, int nx, int ny, 
             double t0, t1;
             cell_interval(&ray, c, &t0, &t1);
             cell_result r;
-            test_cell(vol, &ray, c, t0, t1, iso, &r);
+            flat_src src = {{flat_fetch}, vol, nx, ny};
+            float fc[8];
+            flat_fetch(&src.base, c, fc);
+            test_cell(fc, &ray, c, t0, t1, iso, &r);
             if (r.hit) { found_hit = 1; *hit_idx = n - 1; }
         }
     } while (next_cell(&ray, c));
