@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events in the timed region")
     ap.add_argument("--batch-reps", type=int, default=3, help="repetitions of the batched orbit (0 = skip)")
     ap.add_argument("--poll-every", type=int, default=2)
+    ap.add_argument("--workload", default="fourier", choices=("fourier", "rm", "batched", "serving"),
+                    help="fourier (default: the headline line), rm (2048x2048x1920 RM-like), batched (64 mixed "
+                         "requests, autotuned) or serving (Poisson arrivals, continuous batching)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, copy this many MiB device to device once (the plain copy "
                          "kernel that calibrates the FETCH_SIZE/WRITE_SIZE counters)")
@@ -167,6 +170,12 @@ def main():
     from paper_2309_10212_amd import spr
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "rm":
+        return run_rm(args)
+    if args.workload == "batched":
+        return run_batched(args)
+    if args.workload == "serving":
+        return run_serving(args)
     field, stream, iso, cams = make_inputs(args)
     n = args.n
     ctx = spr.Context(device=0, cache_bytes=args.cache_bytes, spec_cap=args.spec_cap)
@@ -335,6 +344,135 @@ def main():
     vol.free()
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def _line(metric_value, ms_step, steps, warmup, workload_cfg, extra, dtype="f64"):
+    out = {"metric": METRIC, "value": round(metric_value, 1), "unit": "rays/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": workload_cfg}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def run_rm(args):
+    """RM-like mixing layer, 2048x2048x1920 at 2 bits/value, 1280x720, isovalues
+    64/128/192, speculation cap 64, cache 2*10^9 bytes.  One step = one render
+    request (initial rays + passes to completion) at the next (isovalue, orbit
+    view); the grids are built once at load (their time is load_ms)."""
+    import numpy as np
+    import torch
+    import volgen
+    from paper_2309_10212_amd import spr
+    NX, NY, NZ, R = 2048, 2048, 1920, 2
+    t0 = time.perf_counter()
+    stream = volgen.rm_encode(NX, NY, NZ, R, seed=3)
+    log(f"[bench] RM-like stream {stream.nbytes} B in {time.perf_counter() - t0:.1f}s")
+    cams = [volgen.orbit_camera(NX, NY, NZ, seed=3, k=k, npos=10) for k in range(10)]
+    isos = (64.0, 128.0, 192.0)
+    ctx = spr.Context(device=0, cache_bytes=2 * 10**9, spec_cap=64)
+    vol = ctx.load_volume(stream, (NX, NY, NZ), R)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vol.build_grids()
+    torch.cuda.synchronize()
+    load_ms = (time.perf_counter() - t0) * 1e3
+
+    def step(i):
+        r = spr.Render(vol, cams[i % 10], isos[i % 3], args.w, args.h, spec_cap=64)
+        r.run()
+        info = r.info()
+        r.free()
+        return info
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    c0 = ctx.counters()
+    t0 = time.perf_counter()
+    infos = [step(args.warmup + i) for i in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    c1 = ctx.counters()
+    rays = sum(i["rays_entered"] for i in infos)
+    passes = sum(i["passes"] for i in infos)
+    cur, peak = ctx.mem_stats()
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        pix = np.random.default_rng(0).choice(args.w * args.h, 20000, replace=False).astype(np.uint32)
+        t0 = time.perf_counter()
+        ref = oracle.render_stream(stream, (NX, NY, NZ), R, cams[0], isos[0], args.w, args.h, pixels=pix)
+        dt = time.perf_counter() - t0
+        ent = int(ref["entered"].sum())
+        cpu = {"value": round(ent / dt, 1), "unit": "rays/s", "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+               "kind": "oracle", "sample": f"20000 seeded pixels of view 0 at iso 64 ({ent} entered), blocks decoded on "
+                                           "demand (the decoded volume, 32 GB, is not materialised)"}
+    _line(rays / el, el * 1e3 / args.steps, args.steps, args.warmup,
+          {"workload": "rm2048x2048x1920_rate2_1280x720_cap64", "volume": "RM-like mixing layer, 0..255 as float32, 2 bits/value",
+           "isovalues": list(isos), "cache_bytes": 2 * 10**9, "step": "one render request to completion (grids built once at load)"},
+          {"ms_per_pass": round(el * 1e3 / max(passes, 1), 4), "passes_per_step": passes / args.steps, "load_ms": round(load_ms, 3),
+           "blocks_decoded_per_s": round((c1["blocks_decoded"] - c0["blocks_decoded"]) / el, 1), "peak_mem_bytes": peak,
+           "roofline": None, "cpu_baseline": cpu})
+    vol.free()
+    ctx.close()
+
+
+def run_batched(args):
+    """The batched workload: 64 seeded requests over a pool of 8 volumes (blobs
+    and Fourier fields, 128^3..1024^3, float32 or u8 levels, 2/4/8 bits/value)
+    at mixed image sizes; the autotuner picks the speculation cap and the
+    raytrace tuning on a sample; then the 64 requests run as one graph-replayed
+    batch, and one at a time through the plain path with the same settings."""
+    import torch
+    from paper_2309_10212_amd import autotune, spr
+    from volgen import workloads
+    t0 = time.perf_counter()
+    pool = workloads.make_pool()
+    reqs = workloads.make_requests(pool, 64)
+    log(f"[bench] pool of {len(pool)} volumes, {len(reqs)} requests ({time.perf_counter() - t0:.1f}s)")
+    ctx = spr.Context(device=0, cache_bytes=4 * 10**9, spec_cap=16)
+    vols = [ctx.load_volume(p.stream, p.dims, p.rate) for p in pool]
+    best, table = autotune.autotune(ctx, vols, reqs, sample=8)
+    log(f"[bench] autotuned: {best}")
+    # batched: one untimed run, then the timed one
+    _, _, _, rs = autotune.run_batch(ctx, vols, reqs, best.spec_cap, args.poll_every)
+    for r in rs:
+        r.free()
+    dt_b, rays_b, passes_b, rs = autotune.run_batch(ctx, vols, reqs, best.spec_cap, args.poll_every)
+    for r in rs:
+        r.free()
+    # plain: the same requests one at a time
+    def plain():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rays = 0
+        for q in reqs:
+            r = spr.Render(vols[q.vol], q.cam, q.iso, q.w, q.h, spec_cap=best.spec_cap)
+            r.run()
+            rays += r.info()["rays_entered"]
+            r.free()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, rays
+    plain()
+    dt_p, rays_p = plain()
+    cur, peak = ctx.mem_stats()
+    _line(rays_b / dt_b, dt_b * 1e3, 1, 1,
+          {"workload": "batched64_pool8_autotuned", "requests": len(reqs),
+           "pool": [p.name for p in pool], "cache_bytes": 4 * 10**9,
+           "step": "the 64 requests as one batch, from render set-up to the last pass"},
+          {"plain_rays_per_s": round(rays_p / dt_p, 1), "vs_plain": round((rays_b / dt_b) / (rays_p / dt_p), 3),
+           "batched_passes": passes_b, "plain_ms": round(dt_p * 1e3, 3),
+           "tuning": {"spec_cap": best.spec_cap, "pairs_per_wg": best.pairs_per_wg, "slot_tile": best.slot_tile},
+           "autotune_table": [{"spec_cap": c.spec_cap, "pairs_per_wg": c.pairs_per_wg, "slot_tile": c.slot_tile,
+                               "rays_per_s": round(c.rays_per_s, 1)} for c in table],
+           "peak_mem_bytes": peak, "roofline": None, "cpu_baseline": None})
+    for v in vols:
+        v.free()
+    ctx.close()
+
+
+def run_serving(args):
+    raise SystemExit("serving workload: not built yet")
 
 
 if __name__ == "__main__":

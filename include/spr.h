@@ -169,6 +169,19 @@ spr_status spr_ctx_profile(spr_ctx *ctx, int enable, int reset);
 /* Copy up to max per-kernel totals (synchronises); *n = kernels reported. */
 spr_status spr_ctx_kernel_times(spr_ctx *ctx, spr_kernel_time *out, uint32_t max, uint32_t *n);
 
+/* Launch tuning of the block raytrace (Sec. 3.7, Sec. 4.3), for batching and
+ * the autotuner: each workgroup takes pairs_per_wg sorted pairs (128 or 256)
+ * and stages the dual grids of up to slot_tile distinct blocks in LDS (16 or
+ * 32).  The image does not depend on either.  Applies to passes enqueued
+ * after the call (captured pass graphs are re-recorded).  Defaults 256 / 32.
+ * SPR_E_INVALID for other values. */
+typedef struct {
+    uint32_t pairs_per_wg;
+    uint32_t slot_tile;
+} spr_tuning;
+spr_status spr_ctx_set_tuning(spr_ctx *ctx, const spr_tuning *t);
+spr_status spr_ctx_get_tuning(spr_ctx *ctx, spr_tuning *out);
+
 /* ----------------------------------------------------------------- volume */
 /* Upload a compressed volume and build its macrocell grids (Sec. 3.1): every
  * block is decoded once to get its value range; the fine grid (one cell per

@@ -53,6 +53,7 @@ struct spr_ctx {
     hipStream_t stream = nullptr;
     spr_allocator alloc{};
     uint32_t spec_cap = 64;
+    uint32_t rt_tile = 256, rt_lb = 32;   // raytrace launch tuning (spr_ctx_set_tuning)
     size_t mem_cur = 0, mem_peak = 0;
     PassCtl *ctl = nullptr;
     VolDev *d_vols = nullptr;
@@ -214,7 +215,21 @@ PassGrids grids_for(const spr_ctx *c, uint64_t max_A, uint64_t max_P) {
     pg.assign = 256;
     pg.scatter = g(max_P, 256, 2048);
     pg.decode = g(8 * max_P, 64, 1024);
+    pg.max_P = max_P;
+    pg.rt_tile = c->rt_tile;
+    pg.rt_lb = c->rt_lb;
+    pg.rt = g(max_P, c->rt_tile, 4096);
     return pg;
+}
+
+// The launch shape with the context's current raytrace tuning.
+PassGrids tuned(const spr_ctx *c, const PassGrids &g0) {
+    PassGrids g = g0;
+    g.rt_tile = c->rt_tile;
+    g.rt_lb = c->rt_lb;
+    uint64_t x = (g.max_P + c->rt_tile - 1) / c->rt_tile;
+    g.rt = (uint32_t)(x < 1 ? 1 : (x > 4096 ? 4096 : x));
+    return g;
 }
 
 spr_status ensure_work(spr_ctx *c, uint64_t P) {
@@ -285,7 +300,7 @@ spr_status graph_pass(spr_ctx *c, const Table &T, const PassGrids &g, hipGraph_t
         if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
         if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
         HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = launch_pass(c->cap_stream, c->ctl, T, c->d_vols, c->work, c->cache, g, nullptr);
+        hipError_t e = launch_pass(c->cap_stream, c->ctl, T, c->d_vols, c->work, c->cache, tuned(c, g), nullptr);
         hipGraph_t gr = nullptr;
         hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -339,7 +354,7 @@ spr_status prof_flush(spr_ctx *c) {
 spr_status run_pass(spr_ctx *c, const Table &T, const PassGrids &g) {
     hipEvent_t *ev = nullptr;
     if (c->prof) CHK(prof_begin(c, PASS_KERNELS, PASS_SLOTS, &ev));
-    HIPCHK(launch_pass(c->stream, c->ctl, T, c->d_vols, c->work, c->cache, g, ev));
+    HIPCHK(launch_pass(c->stream, c->ctl, T, c->d_vols, c->work, c->cache, tuned(c, g), ev));
     return SPR_OK;
 }
 
@@ -496,6 +511,27 @@ spr_status spr_ctx_kernel_times(spr_ctx *c, spr_kernel_time *out, uint32_t max, 
         out[k].launches = c->prof_n[k];
     }
     *n = k;
+    return SPR_OK;
+}
+
+spr_status spr_ctx_set_tuning(spr_ctx *c, const spr_tuning *t) {
+    if (!c || !t) return fail(SPR_E_INVALID, "null argument");
+    if (t->pairs_per_wg != 128 && t->pairs_per_wg != 256)
+        return fail(SPR_E_INVALID, "pairs_per_wg must be 128 or 256 (got %u)", t->pairs_per_wg);
+    if (t->slot_tile != 16 && t->slot_tile != 32)
+        return fail(SPR_E_INVALID, "slot_tile must be 16 or 32 (got %u)", t->slot_tile);
+    if (t->pairs_per_wg != c->rt_tile || t->slot_tile != c->rt_lb) {
+        c->rt_tile = t->pairs_per_wg;
+        c->rt_lb = t->slot_tile;
+        c->work_gen++;   // captured pass graphs are re-recorded with the new shape
+    }
+    return SPR_OK;
+}
+
+spr_status spr_ctx_get_tuning(spr_ctx *c, spr_tuning *out) {
+    if (!c || !out) return fail(SPR_E_INVALID, "null argument");
+    out->pairs_per_wg = c->rt_tile;
+    out->slot_tile = c->rt_lb;
     return SPR_OK;
 }
 

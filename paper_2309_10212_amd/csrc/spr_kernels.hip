@@ -924,16 +924,16 @@ __device__ __forceinline__ float slot_value(const float *slots, const uint32_t n
     return slots[(size_t)s * 64 + ((lx & 3) + 4 * (ly & 3) + 16 * (lz & 3))];
 }
 
-// A 256-pair tile of the sorted pairs covers runs of a few blocks.  The
-// workgroup stages the 5^3 dual grid of each distinct block of the tile
-// (up to RT_LB blocks) into LDS once - the block's 4^3 samples plus the +x/+y/
-// +z face, edge and corner samples of its neighbours (Sec. 3.7) - and every
-// pair then reads its cell corners from LDS.  Pairs of blocks beyond RT_LB in
-// a tile read the slots directly.
-constexpr int RT_TILE = 256;
-constexpr int RT_LB = 32;
-
-__global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, const VolDev *vols, Work W, Cache C) {
+// A tile of RT_TILE sorted pairs (one workgroup; 128 or 256) covers runs of
+// a few blocks.  The workgroup stages the 5^3 dual grid of each distinct
+// block of the tile (up to RT_LB blocks: 16 or 32) into LDS once - the
+// block's 4^3 samples plus the +x/+y/+z face, edge and corner samples of its
+// neighbours (Sec. 3.7) - and every pair then reads its cell corners from
+// LDS.  Pairs of blocks beyond RT_LB in a tile read the slots directly.  Both
+// sizes are launch tuning: results do not depend on them.
+template <int RT_TILE, int RT_LB>
+__global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, const VolDev *vols, Work W,
+                                                                     Cache C) {
     __shared__ float s_grid[RT_LB][128];
     __shared__ uint32_t s_nsl[RT_LB][8];
     __shared__ int s_bb[RT_LB][4];
@@ -1386,7 +1386,11 @@ hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev
     mark(); hipLaunchKernelGGL(k_evict, dim3(g.slots), dim3(256), 0, s, ctl, vols, C);
     mark(); hipLaunchKernelGGL(k_assign_scatter, dim3(g.assign + g.scatter), dim3(256), 0, s, ctl, T, vols, W, C, g.assign);
     mark(); hipLaunchKernelGGL(k_decode, dim3(g.decode), dim3(64), 0, s, ctl, vols, W, C);
-    mark(); hipLaunchKernelGGL(k_raytrace, dim3(g.pairs), dim3(RT_TILE), 0, s, ctl, T, vols, W, C);
+    mark();
+    if (g.rt_tile == 128 && g.rt_lb == 16) hipLaunchKernelGGL((k_raytrace<128, 16>), dim3(g.rt), dim3(128), 0, s, ctl, T, vols, W, C);
+    else if (g.rt_tile == 128) hipLaunchKernelGGL((k_raytrace<128, 32>), dim3(g.rt), dim3(128), 0, s, ctl, T, vols, W, C);
+    else if (g.rt_lb == 16) hipLaunchKernelGGL((k_raytrace<256, 16>), dim3(g.rt), dim3(256), 0, s, ctl, T, vols, W, C);
+    else hipLaunchKernelGGL((k_raytrace<256, 32>), dim3(g.rt), dim3(256), 0, s, ctl, T, vols, W, C);
     mark(); hipLaunchKernelGGL(k_composite, dim3(g.rays), dim3(256), 0, s, ctl, T, vols);
     mark(); hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, s, ctl, T, 0);
     mark(); hipLaunchKernelGGL(k_compact, dim3(g.rays), dim3(256), 0, s, ctl, T);

@@ -17,6 +17,10 @@ struct PassGrids {
     uint32_t assign;    // 256-thread groups assigning slots to misses
     uint32_t scatter;   // 256-thread groups scattering pairs
     uint32_t decode;    // 64-thread groups decoding misses (one thread per block)
+    uint32_t rt;        // raytrace workgroups
+    uint32_t rt_tile;   // sorted pairs per raytrace workgroup: 128 or 256
+    uint32_t rt_lb;     // blocks staged in LDS per raytrace tile: 16 or 32
+    uint64_t max_P;     // pair capacity the shape was made for
 };
 
 hipError_t launch_decode_ids(hipStream_t s, const VolDev &V, const uint32_t *ids, uint32_t n, float *out);

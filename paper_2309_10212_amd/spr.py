@@ -85,6 +85,10 @@ class RenderInfo(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("pairs_per_wg", ctypes.c_uint32), ("slot_tile", ctypes.c_uint32)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("total_ms", ctypes.c_double), ("launches", ctypes.c_uint64)]
 
@@ -102,6 +106,8 @@ SIGNATURES = [
     ("spr_ctx_counters", _ST, [_P, ctypes.POINTER(Counters)]),
     ("spr_ctx_profile", _ST, [_P, ctypes.c_int, ctypes.c_int]),
     ("spr_ctx_kernel_times", _ST, [_P, ctypes.POINTER(KernelTime), _U32, ctypes.POINTER(_U32)]),
+    ("spr_ctx_set_tuning", _ST, [_P, ctypes.POINTER(Tuning)]),
+    ("spr_ctx_get_tuning", _ST, [_P, ctypes.POINTER(Tuning)]),
     ("spr_volume_load", _ST, [_P, _P, ctypes.c_size_t, ctypes.POINTER(_VolumeDesc), ctypes.POINTER(_P)]),
     ("spr_volume_free", _ST, [_P]),
     ("spr_volume_build_grids", _ST, [_P]),
@@ -221,6 +227,15 @@ class Context:
 
     def profile(self, enable: bool, reset: bool = False):
         _chk(load_library().spr_ctx_profile(self.h, int(enable), int(reset)), "spr_ctx_profile")
+
+    def set_tuning(self, pairs_per_wg: int, slot_tile: int):
+        t = Tuning(pairs_per_wg, slot_tile)
+        _chk(load_library().spr_ctx_set_tuning(self.h, ctypes.byref(t)), "spr_ctx_set_tuning")
+
+    def tuning(self):
+        t = Tuning()
+        _chk(load_library().spr_ctx_get_tuning(self.h, ctypes.byref(t)), "spr_ctx_get_tuning")
+        return {"pairs_per_wg": t.pairs_per_wg, "slot_tile": t.slot_tile}
 
     def kernel_times(self):
         arr = (KernelTime * 64)()
