@@ -155,6 +155,7 @@ def main():
     ap.add_argument("--workload", default="fourier", choices=("fourier", "rm", "batched", "serving"),
                     help="fourier (default: the headline line), rm (2048x2048x1920 RM-like), batched (64 mixed "
                          "requests, autotuned) or serving (Poisson arrivals, continuous batching)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="length of the serving arrival stream")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, copy this many MiB device to device once (the plain copy "
                          "kernel that calibrates the FETCH_SIZE/WRITE_SIZE counters)")
@@ -472,7 +473,51 @@ def run_batched(args):
 
 
 def run_serving(args):
-    raise SystemExit("serving workload: not built yet")
+    """Serving: Poisson arrivals (lambda = 200/s over --serve-seconds, seed 7)
+    of orbit-step (70%) and isovalue-change (30%) requests at 1280x720 or
+    1920x1080 over three resident volumes (the 512^3 Fourier field at 4
+    bits/value, a 1024^3 Fourier field, seed 4, at 4 bits/value, and the
+    2048x2048x1920 RM-like volume at 2 bits/value), one shared 4*10^9-byte
+    cache, continuous batching with admission by cache memory."""
+    import torch
+    import volgen
+    from paper_2309_10212_amd import serve, spr
+    from volgen import workloads
+    t0 = time.perf_counter()
+    f1 = volgen.fourier(512, 512, 512, seed=2, nmode=64, kmax=24, period=512.0)
+    r1 = (volgen.percentile_value(f1, 0.1), volgen.percentile_value(f1, 0.9))
+    s1 = volgen.encode(f1, 4)
+    del f1
+    f2 = volgen.fourier(1024, 1024, 1024, seed=4, nmode=64, kmax=24, period=1024.0)
+    r2 = (volgen.percentile_value(f2, 0.1), volgen.percentile_value(f2, 0.9))
+    s2 = volgen.encode(f2, 4)
+    del f2
+    s3 = volgen.rm_encode(2048, 2048, 1920, 2, seed=3)
+    dims = [(512, 512, 512), (1024, 1024, 1024), (2048, 2048, 1920)]
+    arr = workloads.serving_arrivals(dims, [r1, r2, (64.0, 192.0)], lam=200.0, span_s=args.serve_seconds, seed=7)
+    log(f"[bench] serving inputs and {len(arr)} arrivals ({time.perf_counter() - t0:.1f}s)")
+    ctx = spr.Context(device=0, cache_bytes=4 * 10**9, spec_cap=16)
+    vols = [ctx.load_volume(s, d, r) for s, d, r in zip((s1, s2, s3), dims, (4, 4, 2))]
+    torch.cuda.synchronize()
+    srv = serve.Server(ctx, vols, cache_bytes=4 * 10**9, max_requests=32)
+    # warm-up: a short stream before the measured one
+    warm = workloads.serving_arrivals(dims, [r1, r2, (64.0, 192.0)], lam=200.0, span_s=1.0, seed=8)
+    srv.run(warm)
+    results, st = srv.run(arr)
+    cur, peak = ctx.mem_stats()
+    _line(st["rays_per_s"], st["makespan_s"] * 1e3, 1, 1,
+          {"workload": f"serving_poisson200_{args.serve_seconds:g}s_3vol", "arrivals": len(arr), "lambda_per_s": 200.0,
+           "volumes": ["fourier512_rate4", "fourier1024_rate4", "rm2048x2048x1920_rate2"], "cache_bytes": 4 * 10**9,
+           "images": "1280x720 / 1920x1080 (50/50)", "mix": "70% orbit step, 30% isovalue change",
+           "step": "the whole arrival stream, first arrival to last completion"},
+          {"pass_latency_ms_p50": round(st["pass_latency_ms_p50"], 3), "pass_latency_ms_p99": round(st["pass_latency_ms_p99"], 3),
+           "request_latency_ms_p50": round(st["request_latency_ms_p50"], 3), "max_concurrent": st["max_concurrent"],
+           "batched_passes": st["passes"], "makespan_s": round(st["makespan_s"], 3),
+           "peak_mem_bytes": peak, "roofline": None, "cpu_baseline": None})
+    srv.close()
+    for v in vols:
+        v.free()
+    ctx.close()
 
 
 if __name__ == "__main__":

@@ -267,6 +267,18 @@ spr_status spr_batch_pass(spr_batch *b, uint32_t *n_unfinished);
 /* Passes until every render is done or max_passes; polls completion every
  * poll_every passes (0 -> 1).  Synchronises. */
 spr_status spr_batch_run(spr_batch *b, uint32_t max_passes, uint32_t poll_every, uint32_t *passes_run);
+/* Progress of one batch member after the last pass. */
+typedef struct {
+    uint32_t n_active;    /* rays still active (0 = finished) */
+    uint32_t passes;      /* passes run */
+    uint32_t last_pairs;  /* ray-block pairs of the last pass */
+    uint32_t n_spec;      /* N_spec for the next pass (Sec. 4) */
+} spr_member_state;
+/* Every member's progress, in member order (n = member count), and the
+ * active blocks of the last pass: the cache slots it needed (Sec. 3.4),
+ * which a server's admission control estimates from.  One gather kernel and
+ * one copy; synchronises. */
+spr_status spr_batch_state(spr_batch *b, spr_member_state *out, uint32_t n, uint32_t *active_blocks);
 spr_status spr_batch_free(spr_batch *b);
 
 /* Thread-local message of the last failing call on this thread. */

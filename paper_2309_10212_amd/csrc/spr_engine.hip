@@ -118,6 +118,9 @@ struct spr_batch {
     hipGraphExec_t exec = nullptr;
     uint64_t graph_gen = ~0ull;
     uint64_t max_pixels = 0;
+    uint4 *d_state = nullptr;   // cap + 1 gathered member records (k_gather_state)
+    uint4 *h_state = nullptr;   // pinned copy
+    bool state_fresh = false;   // h_state reflects the last pass and the current members
 };
 
 namespace {
@@ -981,11 +984,19 @@ spr_status spr_batch_create_empty(spr_ctx *c, uint32_t max_requests, uint64_t ma
     b->max_pixels = max_pixels;
     spr_status st = alloc_table(c, max_requests, A, P, b->table);
     if (st == SPR_OK) st = dalloc(c, max_requests, &b->table.reqs);
+    if (st == SPR_OK) st = dalloc(c, (size_t)max_requests + 1, &b->d_state);
+    if (st == SPR_OK && hipHostMalloc((void **)&b->h_state, sizeof(uint4) * ((size_t)max_requests + 1),
+                                      hipHostMallocDefault) != hipSuccess) {
+        b->h_state = nullptr;
+        st = fail(SPR_E_OOM, "pinned host allocation failed");
+    }
     if (st == SPR_OK) st = ensure_work(c, P);
     if (st == SPR_OK) st = set_table_count(c, b->table, 0);
     if (st != SPR_OK) {
         free_table(c, b->table);
         dfree(c, b->table.reqs, max_requests);
+        dfree(c, b->d_state, (size_t)max_requests + 1);
+        if (b->h_state) (void)hipHostFree(b->h_state);
         delete b;
         return st;
     }
@@ -1019,6 +1030,7 @@ spr_status spr_batch_set(spr_batch *b, uint32_t n, spr_render *const *renders) {
     for (auto *r : b->renders) r->batch = nullptr;
     b->renders.assign(renders, renders + n);
     for (auto *r : b->renders) r->batch = b;
+    b->state_fresh = false;
     return SPR_OK;
 }
 
@@ -1047,39 +1059,42 @@ static spr_status batch_launch(spr_batch *b) {
     if (c->prof) CHK(run_pass(c, b->table, b->grids));
     else CHK(graph_pass(c, b->table, b->grids, b->graph, b->exec, b->graph_gen));
     for (auto *r : b->renders) r->started = true;
+    b->state_fresh = false;
+    return SPR_OK;
+}
+
+// Gather every member's progress (one kernel, one copy) into b->h_state.
+static spr_status batch_gather(spr_batch *b) {
+    spr_ctx *c = b->ctx;
+    const uint32_t n = (uint32_t)b->renders.size();
+    HIPCHK(launch_gather_state(c->stream, c->ctl, b->table, n, b->d_state));
+    HIPCHK(hipMemcpyAsync(b->h_state, b->d_state, sizeof(uint4) * ((size_t)n + 1), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    b->state_fresh = true;
     return SPR_OK;
 }
 
 static spr_status batch_unfinished(spr_batch *b, uint32_t *n_unfinished) {
-    spr_ctx *c = b->ctx;
-    uint32_t n = (uint32_t)b->renders.size();
-    if (n == 0) {
-        HIPCHK(hipStreamSynchronize(c->stream));
-        *n_unfinished = 0;
-        return SPR_OK;
-    }
-    char *dst = (char *)c->pinned + 1024;
-    if (n * sizeof(uint32_t) > 2048) {
-        // large batches: read in chunks through the staging area
-        uint32_t cnt = 0;
-        for (auto *r : b->renders) {
-            ReqState s;
-            CHK(read_state(c, r->d_st, &s));
-            cnt += s.n_act > 0;
-        }
-        *n_unfinished = cnt;
-        return SPR_OK;
-    }
-    for (uint32_t i = 0; i < n; ++i)
-        HIPCHK(hipMemcpyAsync(dst + 4 * i, &b->renders[i]->d_st->n_act, 4, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(batch_gather(b));
     uint32_t cnt = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        uint32_t v;
-        memcpy(&v, dst + 4 * i, 4);
-        cnt += v > 0;
-    }
+    for (size_t i = 0; i < b->renders.size(); ++i) cnt += b->h_state[i].x > 0;
     *n_unfinished = cnt;
+    return SPR_OK;
+}
+
+spr_status spr_batch_state(spr_batch *b, spr_member_state *out, uint32_t n, uint32_t *active_blocks) {
+    if (!b || (n && !out)) return fail(SPR_E_INVALID, "null argument");
+    if (n != b->renders.size()) return fail(SPR_E_INVALID, "n = %u, the batch has %zu members", n, b->renders.size());
+    HIPCHK(hipSetDevice(b->ctx->device));
+    if (!b->state_fresh) CHK(batch_gather(b));
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint4 v = b->h_state[i];
+        out[i].n_active = v.x;
+        out[i].passes = v.y;
+        out[i].last_pairs = v.z;
+        out[i].n_spec = v.w;
+    }
+    if (active_blocks) *active_blocks = b->h_state[n].x;
     return SPR_OK;
 }
 
@@ -1119,6 +1134,8 @@ spr_status spr_batch_free(spr_batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     free_table(c, b->table);
     dfree(c, b->table.reqs, b->table.cap);
+    dfree(c, b->d_state, (size_t)b->table.cap + 1);
+    if (b->h_state) (void)hipHostFree(b->h_state);
     for (auto *r : b->renders) r->batch = nullptr;
     delete b;
     return SPR_OK;

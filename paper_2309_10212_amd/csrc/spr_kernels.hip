@@ -1278,6 +1278,17 @@ __global__ __launch_bounds__(256) void k_compact(PassCtl *ctl, Table T) {
     }
 }
 
+// Progress of the members of a launch table, for the host's scheduler: per
+// request {active rays, passes run, pairs of the last pass, N_spec}, then
+// {active blocks of the last pass, pass stamp, 0, 0}.  One workgroup.
+__global__ void k_gather_state(const PassCtl *ctl, Table T, uint32_t n, uint4 *out) {
+    for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
+        const ReqState *st = T.reqs[r].st;
+        out[r] = make_uint4(st->n_act, st->passes, st->last_pairs, st->n_spec);
+    }
+    if (threadIdx.x == 0) out[n] = make_uint4(ctl->n_actblk, ctl->pass, 0u, 0u);
+}
+
 // Arithmetic probe: fp64 sqrt and division as compiled for the hit test.
 __global__ void k_fp64_ops(const double *x, const double *y, uint64_t n, double *sq, double *dv) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -1321,6 +1332,11 @@ hipError_t launch_load_grids(hipStream_t s, const VolDev &V, hipEvent_t *ev) {
     uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
     mark(); hipLaunchKernelGGL(k_coarse_grid, dim3(grid_for(nc, 256, 1u << 16)), dim3(256), 0, s, V);
     mark();
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_state(hipStream_t s, const PassCtl *ctl, const Table &T, uint32_t n, uint4 *out) {
+    hipLaunchKernelGGL(k_gather_state, dim3(1), dim3(256), 0, s, ctl, T, n, out);
     return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@ hipError_t launch_fp64_ops(hipStream_t s, const double *x, const double *y, uint
 // Load path: block ranges, fine grid, coarse grid.  ev == nullptr: plain
 // launches; else ev[i] is recorded before kernel i and ev[3] after the last.
 hipError_t launch_load_grids(hipStream_t s, const VolDev &V, hipEvent_t *ev = nullptr);
+// Members' progress of a table into out[0..n] (see k_gather_state).
+hipError_t launch_gather_state(hipStream_t s, const PassCtl *ctl, const Table &T, uint32_t n, uint4 *out);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t v);
 hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n, uint64_t v);
 hipError_t launch_iota_u32(hipStream_t s, uint32_t *p, uint64_t n);

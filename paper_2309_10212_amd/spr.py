@@ -89,6 +89,11 @@ class Tuning(ctypes.Structure):
     _fields_ = [("pairs_per_wg", ctypes.c_uint32), ("slot_tile", ctypes.c_uint32)]
 
 
+class MemberState(ctypes.Structure):
+    _fields_ = [("n_active", ctypes.c_uint32), ("passes", ctypes.c_uint32), ("last_pairs", ctypes.c_uint32),
+                ("n_spec", ctypes.c_uint32)]
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("total_ms", ctypes.c_double), ("launches", ctypes.c_uint64)]
 
@@ -129,6 +134,7 @@ SIGNATURES = [
     ("spr_batch_set", _ST, [_P, _U32, ctypes.POINTER(_P)]),
     ("spr_batch_pass", _ST, [_P, ctypes.POINTER(_U32)]),
     ("spr_batch_run", _ST, [_P, _U32, _U32, ctypes.POINTER(_U32)]),
+    ("spr_batch_state", _ST, [_P, ctypes.POINTER(MemberState), _U32, ctypes.POINTER(_U32)]),
     ("spr_batch_free", _ST, [_P]),
     ("spr_last_error", ctypes.c_char_p, []),
     ("spr_version", ctypes.c_char_p, []),
@@ -408,6 +414,14 @@ class Batch:
         n = ctypes.c_uint32()
         _chk(load_library().spr_batch_run(self.h, max_passes, poll_every, ctypes.byref(n)), "spr_batch_run")
         return n.value
+
+    def state(self):
+        """([per-member dicts], active blocks of the last pass)."""
+        n = len(self.renders)
+        arr = (MemberState * max(n, 1))()
+        ab = ctypes.c_uint32()
+        _chk(load_library().spr_batch_state(self.h, arr, n, ctypes.byref(ab)), "spr_batch_state")
+        return [{f: getattr(arr[i], f) for f, _ in MemberState._fields_} for i in range(n)], ab.value
 
     def free(self):
         if self.h:
