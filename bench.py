@@ -225,6 +225,7 @@ def main():
     c1 = ctx.counters()
     ktimes = ctx.kernel_times()
     dc = {k: c1[k] - c0[k] for k in c1}
+    dc["max_active_blocks"] = c1["max_active_blocks"]
     nb_vol = ((n + 3) // 4) ** 3
     dc["load_blocks"] = nb_vol * args.steps
     dc["load_coarse"] = ((((n + 3) // 4) + 3) // 4) ** 3 * args.steps
@@ -338,6 +339,15 @@ def main():
         "counters": dc,
         "kernels_ms_per_launch": {k: round(ms / max(nl, 1), 5) for k, (ms, nl) in ktimes.items()},
         "roofline": roof,
+        "bcmc_proxy": {
+            "blocks_per_view": round(sum(i["bcmc_blocks"] for i in infos) / len(infos), 1),
+            "decoded_blocks_per_view": round(dc["blocks_decoded"] / args.steps, 1),
+            "decoded_ratio": round(sum(i["bcmc_blocks"] for i in infos) / max(dc["blocks_decoded"], 1), 2),
+            "bytes": int(sum(i["bcmc_blocks"] for i in infos) / len(infos) * 256),
+            "cache_bytes_needed": int(dc["max_active_blocks"] * 256),
+            "note": "blocks whose fine range contains the isovalue (what decompressing every block that may hold "
+                    "the surface decodes) vs blocks this build decoded per view, with the block cache warm across "
+                    "the orbit; bytes at 256 B per decoded block vs the largest per-pass active set"},
         "batched": batched,
         "sweep": sweep,
         "cpu_baseline": cpu,

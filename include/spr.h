@@ -133,6 +133,7 @@ typedef struct {
     uint64_t rays;            /* sum over passes of active rays */
     uint64_t pair_slots;      /* sum over passes of N_act * N_spec (R_BID entries written) */
     uint64_t served_pairs;    /* sum over passes of pairs raytraced */
+    uint64_t max_active_blocks; /* largest active-block count of any pass: the cache slots a pass needed */
 } spr_counters;
 
 /* Per-render summary. */
@@ -143,6 +144,8 @@ typedef struct {
     uint32_t n_spec;          /* speculation count of the next pass */
     uint32_t passes;          /* passes run */
     uint64_t pairs;           /* ray-block pairs over all passes */
+    uint64_t bcmc_blocks;     /* blocks whose fine range contains the isovalue: what decompressing every
+                                 block that may hold the surface (the BCMC comparison, Sec. 5) decodes */
 } spr_render_info;
 
 /* Accumulated device time of one kernel of the pass (profiling mode). */

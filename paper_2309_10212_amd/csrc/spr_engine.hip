@@ -483,6 +483,7 @@ spr_status spr_ctx_counters(spr_ctx *c, spr_counters *o) {
     o->rays = p.acc_rays;
     o->pair_slots = p.acc_slots;
     o->served_pairs = p.acc_served;
+    o->max_active_blocks = p.acc_max_active;
     return SPR_OK;
 }
 
@@ -729,6 +730,7 @@ static void free_render_buffers(spr_ctx *c, spr_render *r) {
     dfree(c, r->d_st, 1);
     dfree(c, r->d_req, 1);
     dfree(c, q.cmask64, r->cwords);
+    dfree(c, q.cdist, 2 * r->cwords);
     free_table(c, r->table);
 }
 
@@ -772,6 +774,7 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
             r->cwords = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
         }
         if ((st = dalloc(c, r->cwords, &q.cmask64)) != SPR_OK) break;
+        if ((st = dalloc(c, 2 * r->cwords, &q.cdist)) != SPR_OK) break;
         if ((st = alloc_table(c, 1, round64h(npix), npix, r->table)) != SPR_OK) break;
         st = ensure_work(c, npix);
     } while (0);
@@ -924,6 +927,7 @@ spr_status spr_render_get_info(spr_render *r, spr_render_info *o) {
     o->n_spec = s.n_spec;
     o->passes = s.passes;
     o->pairs = s.tot_pairs;
+    o->bcmc_blocks = s.bcmc;
     return SPR_OK;
 }
 

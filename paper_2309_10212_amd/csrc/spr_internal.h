@@ -63,7 +63,7 @@ struct ReqState {
     uint32_t entered;           // rays that entered the volume (set at the first pass)
     uint32_t pad[2];
     unsigned long long tot_pairs;
-    uint32_t pad2[2];
+    unsigned long long bcmc;    // blocks whose fine range contains the isovalue (set up with the masks)
 };
 
 // Immutable per-render description (camera basis computed on the host).
@@ -83,7 +83,12 @@ struct ReqDev {
     ReqState *st;
     uint64_t *cmask64;          // per coarse cell: bit (bx&3) + 4(by&3) + 16(bz&3) set when that
                                 // block's fine range contains iso (0 when the coarse range does not)
+    uint8_t *cdist;             // per coarse cell: chessboard distance (in coarse cells, capped at
+                                // CD_MAX) to the nearest coarse cell with a nonzero mask; a second
+                                // nc bytes after it are scratch for the separable passes
 };
+
+constexpr int CD_MAX = 15;
 
 // Per-pass control block of a context (counters reset at each pass start).
 struct PassCtl {
@@ -115,7 +120,7 @@ struct PassCtl {
     uint32_t hist[64];
     // cumulative counters since context creation
     unsigned long long acc_passes, acc_decoded, acc_visible, acc_active, acc_pairs, acc_evicted, acc_overflow,
-        acc_rays, acc_slots, acc_served;
+        acc_rays, acc_slots, acc_served, acc_max_active;
 };
 
 // Launch table of a pass: the requests advanced together.

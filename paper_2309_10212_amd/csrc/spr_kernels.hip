@@ -422,11 +422,17 @@ __global__ void k_pass_begin(PassCtl *ctl, Table T, int is_init) {
 // The word is 0 when the coarse range does not contain the isovalue (Sec. 3.1
 // coarse grid), and a zero word lets the traversal skip the whole coarse cell.
 // The walk loads one word per coarse cell and tests blocks in registers.
-__global__ void k_iso_masks(Table T, const VolDev *vols) {
+// The set bits also count the blocks whose fine range contains the isovalue
+// (one atomic per workgroup into the request's state).
+__global__ __launch_bounds__(256) void k_iso_masks(Table T, const VolDev *vols) {
+    __shared__ unsigned long long s_cnt;
     const ReqDev &q = T.reqs[0];
     const VolDev &V = vols[q.vol];
     const float iso = q.iso;
     const uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    unsigned long long my = 0;
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nc; c += (uint64_t)gridDim.x * blockDim.x) {
         uint64_t bits = 0;
         float2 cr = V.coarse[c];
@@ -442,6 +448,49 @@ __global__ void k_iso_masks(Table T, const VolDev *vols) {
             }
         }
         q.cmask64[c] = bits;
+        my += (unsigned long long)__popcll(bits);
+    }
+    if (my) atomicAdd(&s_cnt, my);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) atomicAdd(&q.st->bcmc, s_cnt);
+}
+
+// Empty-space distances (per request, after the masks).  Chessboard distance
+// is separable: with f0 = 0 on coarse cells whose mask is nonzero and CD_MAX
+// elsewhere, f_{a}(c) = min over |k| <= CD_MAX of max(|k|, f_{a-1}(c + k e_a))
+// along x, then y, then z gives, per cell, the distance (capped at CD_MAX) to
+// the nearest nonzero cell.  Capping only underestimates: the walk then jumps
+// less far, never over a nonzero cell.
+__global__ __launch_bounds__(256) void k_cdist_occ(Table T, const VolDev *vols) {
+    const ReqDev &q = T.reqs[0];
+    const VolDev &V = vols[q.vol];
+    const uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    uint8_t *occ = q.cdist + nc;
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nc; c += (uint64_t)gridDim.x * blockDim.x)
+        occ[c] = q.cmask64[c] != 0 ? 0 : (uint8_t)CD_MAX;
+}
+
+__global__ __launch_bounds__(256) void k_cdist_pass(Table T, const VolDev *vols, int axis) {
+    const ReqDev &q = T.reqs[0];
+    const VolDev &V = vols[q.vol];
+    const uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    // x: scratch -> final, y: final -> scratch, z: scratch -> final
+    const uint8_t *src = (axis == 1) ? q.cdist : q.cdist + nc;
+    uint8_t *dst = (axis == 1) ? q.cdist + nc : q.cdist;
+    const int n_a = V.nc[axis];
+    const uint64_t stride = axis == 0 ? 1ull : (axis == 1 ? (uint64_t)V.nc[0] : (uint64_t)V.nc[0] * V.nc[1]);
+    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nc; c += (uint64_t)gridDim.x * blockDim.x) {
+        const int p = (int)((c / stride) % (uint64_t)n_a);
+        int best = CD_MAX;
+        for (int k = -CD_MAX; k <= CD_MAX; ++k) {
+            const int pk = p + k;
+            if (pk < 0 || pk >= n_a) continue;
+            const int v = src[(int64_t)c + (int64_t)k * (int64_t)stride];
+            const int ak = k < 0 ? -k : k;
+            const int d = ak > v ? ak : v;
+            best = d < best ? d : best;
+        }
+        dst[c] = (uint8_t)best;
     }
 }
 
@@ -511,6 +560,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         WaveReq u;
         load_wave_req(q, vols[uni(q.vol)], u);
         const gptr<const uint64_t> cmask = as_global((const uint64_t *)uni(q.cmask64));
+        const gptr<const uint8_t> cdist = as_global((const uint8_t *)uni(q.cdist));
         const gptr<uint32_t> slots = as_global(uni(q.pair_blk) + (size_t)i * ns);
         const uint32_t state = uni(q.ray_state)[pix];
         Ray R;
@@ -556,6 +606,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
             if (ctest) {
                 const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
                 cm = cmask[cid];
+                const int cd = cdist[cid];
                 if (cm != 0) {
                     if (!bvalid) {
 #pragma unroll
@@ -568,6 +619,33 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                         bvalid = true;
                     }
                     ctest = false;
+                } else if (cd >= 2) {
+                    // every coarse cell within cd-1 (chessboard) is empty: leave that box
+                    // in one jump.  t* = the first crossing of one of its faces (or of
+                    // the domain) - the parameter at which a cell-by-cell walk leaves
+                    // the box - and the coarse cell there is the walk's cell: every
+                    // plane with parameter <= t* crossed (cell_at).
+                    const int rr = cd - 1;
+                    double tn = __builtin_inf();
+                    bool domain = false;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const int dir = axis_dir(R, a);
+                        if (dir == 0) continue;
+                        int face = dir > 0 ? cc[a] + rr + 1 : cc[a] - rr;
+                        face = face < 0 ? 0 : (face > u.tc[a] ? u.tc[a] : face);
+                        const double tf = tau_plane(R, LC, a, face);
+                        const bool dom = dir > 0 ? face == u.tc[a] : face == 0;
+                        if (tf < tn) { tn = tf; domain = dom; }
+                        else if (tf == tn) domain = domain || dom;
+                    }
+                    if (tn > R.tx || domain) { alive = false; break; }
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) cc[a] = cell_at(R, LC, a, tn, 0, tchi[a]);
+                    tcur = tn;
+                    bvalid = false;
+                    cvalid = false;
+                    continue;
                 } else {
                     // empty coarse cell: step over it at the coarse level
                     if (!cvalid) {
@@ -1232,6 +1310,7 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
             ctl->acc_rays += ctl->rays;
             ctl->acc_slots += ctl->P;
             ctl->acc_served += ctl->served;
+            if (ctl->n_actblk > ctl->acc_max_active) ctl->acc_max_active = ctl->n_actblk;
         }
     }
     for (uint32_t r = t; r < nreq; r += PE_THREADS) {
@@ -1367,7 +1446,11 @@ hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const V
         if (ev) (void)hipEventRecord(ev[k], s);
         ++k;
     };
-    mark(); hipLaunchKernelGGL(k_iso_masks, dim3(grid_for(mask_words, 256, 8192)), dim3(256), 0, s, T, vols);
+    mark();   // masks, then the empty-space distances (timed together)
+    hipLaunchKernelGGL(k_iso_masks, dim3(grid_for(mask_words, 256, 1024)), dim3(256), 0, s, T, vols);
+    hipLaunchKernelGGL(k_cdist_occ, dim3(grid_for(mask_words, 256, 4096)), dim3(256), 0, s, T, vols);
+    for (int a = 0; a < 3; ++a)
+        hipLaunchKernelGGL(k_cdist_pass, dim3(grid_for(mask_words, 256, 4096)), dim3(256), 0, s, T, vols, a);
     mark(); hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, ctl, T, 1);
     mark(); hipLaunchKernelGGL(k_init_rays, dim3(grid_for(T.max_A, 256, 16384)), dim3(256), 0, s, ctl, T, vols);
     mark(); hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, s, ctl, T, 1);

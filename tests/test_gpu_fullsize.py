@@ -64,6 +64,7 @@ def test_fullsize_grids_decode_and_render(fourier):
             for key in ("n_active", "n_spec", "pairs", "visible", "active_blocks", "terminated"):
                 assert g[key] == o[key], (k, cap, p, key, g, o)
         dt = _cmp(r.hits(), r.image(), oracle.render(dec, cams[k], iso, W, H), f"view {k} cap {cap}")
+        assert r.info()["bcmc_blocks"] == oracle.blocks_containing(rf, iso)
         print(f"view {k} cap {cap}: {len(got)} passes, max |dt| {dt:.3g}", flush=True)
         r.free()
     vol.free()

@@ -109,7 +109,39 @@ def test_tiny_render_and_pass_counters(ctx, cap):
     for p, (g, o) in enumerate(zip(got, sched)):
         for k in ("n_active", "n_spec", "pairs", "visible", "active_blocks", "terminated"):
             assert g[k] == o[k], (p, k, g, o)
+    # the BCMC-proxy count: blocks whose fine range contains the isovalue
+    _, fine, _ = oracle.grids(dec)
+    assert r.info()["bcmc_blocks"] == oracle.blocks_containing(fine, iso)
     r.free()
+    vol.free()
+
+
+@pytest.mark.parametrize("cap", [1, 64])
+def test_sparse_volume_empty_space_jumps(ctx, cap):
+    """Two small blobs in a 256^3 volume: most coarse cells are far from any
+    candidate block, so the traversal jumps over empty space.  Every pixel and
+    every per-pass counter must equal the oracle (which marches every cell)."""
+    from paper_2309_10212_amd import spr
+    n = 256
+    f = volgen.blobs(n, n, n, seed=21, nblob=2)
+    s = volgen.encode(f, 8)
+    dec = oracle.decode_volume(s, (n, n, n), 8)
+    vol = ctx.load_volume(s, (n, n, n), 8)
+    for k in range(2):
+        cam = volgen.orbit_camera(n, n, n, seed=21 + k)
+        iso = 0.3
+        r = spr.Render(vol, cam, iso, 160, 120, spec_cap=cap)
+        got = []
+        while not r.done():
+            got.append(r.pass_(stats=True))
+            assert len(got) < 400
+        sched = oracle.schedule(dec, cam, iso, 160, 120, cap)
+        assert len(got) == len(sched), (k, len(got), len(sched))
+        for p, (g, o) in enumerate(zip(got, sched)):
+            for key in ("n_active", "n_spec", "pairs", "visible", "active_blocks", "terminated"):
+                assert g[key] == o[key], (k, p, key, g, o)
+        _cmp_hits(r.hits(), r.image(), oracle.render(dec, cam, iso, 160, 120), f"sparse view {k} cap {cap}")
+        r.free()
     vol.free()
 
 
