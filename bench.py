@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 METRIC = "rays/s & ms/pass at 1280x720, batched vs plain, same accuracy; blocks decoded/s"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2309_10212_amd/csrc/spr_kernels.hip", "paper_2309_10212_amd/csrc/spr_internal.h",
-                  "paper_2309_10212_amd/csrc/spr_launch.h")
+                  "paper_2309_10212_amd/csrc/spr_launch.h", "paper_2309_10212_amd/csrc/spr_codec.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fourier512_rate4_1280x720.txt")
 
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspr.so")
 SOURCES = ["spr_kernels.hip", "spr_engine.hip"]
-HEADERS = ["spr_internal.h", "spr_launch.h"]
+HEADERS = ["spr_internal.h", "spr_launch.h", "spr_codec.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -8,185 +8,9 @@
 // decode + pair scatter, block raytrace, depth composite, ray counting and
 // ordered compaction with the N_spec update.
 #include "spr_launch.h"
+#include "spr_codec.h"
 
 namespace spr {
-
-// ------------------------------------------------- codec: coefficient order --
-// Embedded coding visits coefficient positions sorted by the sum of their
-// per-axis transform levels (L:0, H:1, h0:2, h1:2), ties by raster index.
-struct OrderTable {
-    uint8_t ord[64];
-};
-
-static constexpr OrderTable make_order() {
-    OrderTable t{};
-    int lev[4] = {0, 1, 2, 2};
-    int n = 0;
-    for (int s = 0; s <= 6; ++s)
-        for (int i = 0; i < 64; ++i)
-            if (lev[i & 3] + lev[(i >> 2) & 3] + lev[(i >> 4) & 3] == s) t.ord[n++] = (uint8_t)i;
-    return t;
-}
-
-__constant__ OrderTable c_order = make_order();
-
-// --------------------------------------------------- codec: thread decode --
-// One thread decodes one block, bit by bit, in the order the format defines
-// (the same control flow as the encoder, mirrored).  The record words are
-// staged in LDS and the next one is prefetched a word ahead; magnitudes of the
-// order-space coefficients live in LDS, interleaved so that a wave touching
-// coefficient j hits distinct banks; the significance and sign masks are
-// 64-bit registers.  The inverse integer transform then runs on 64 int32
-// values in registers with compile-time indices.
-
-static constexpr OrderTable kOrder = make_order();
-
-// 32-bit two's complement lifting (the codec's integer arithmetic): sums
-// wrap modulo 2^32 (done in unsigned arithmetic), halving is an arithmetic
-// shift (rounds toward minus infinity).
-__device__ __forceinline__ int32_t half32(int32_t x) { return x >> 1; }
-__device__ __forceinline__ int32_t add32(int32_t a, int32_t b) { return (int32_t)((uint32_t)a + (uint32_t)b); }
-__device__ __forceinline__ int32_t sub32(int32_t a, int32_t b) { return (int32_t)((uint32_t)a - (uint32_t)b); }
-
-__device__ __forceinline__ void inv4(int32_t &p0, int32_t &p1, int32_t &p2, int32_t &p3) {
-    int32_t L = p0, H = p1, h0 = p2, h1 = p3;
-    int32_t l1 = sub32(L, half32(H));
-    int32_t l0 = add32(l1, H);
-    int32_t a1 = sub32(l0, half32(h0));
-    int32_t a0 = add32(a1, h0);
-    int32_t a3 = sub32(l1, half32(h1));
-    int32_t a2 = add32(a3, h1);
-    p0 = a0; p1 = a1; p2 = a2; p3 = a3;
-}
-
-// Per-wave LDS of the thread decoder: record words (RWMAX + 2 per lane, the
-// tail reads as 0) and 64 magnitudes per lane.
-template <int RWMAX>
-struct DecodeLds {
-    uint32_t rec[(RWMAX + 2) * 64];
-    uint32_t mag[64 * 64];
-};
-
-__device__ __forceinline__ uint32_t low_bit(uint64_t x) { return (uint32_t)__ffsll((unsigned long long)x) - 1u; }
-
-// Decodes the record into q[64] (raster order) and the block exponent.
-// Returns false for an all-zero block (q untouched).  L: this wave's LDS;
-// lane: lane id within the wave; rate: 1..16 bits per value (RWMAX >= 2 rate).
-//
-// The decoder is one flat loop in which every active lane consumes exactly
-// one bit per iteration; the meaning of the bit depends on the lane's mode:
-//   REF   refinement bit of the next significant coefficient,
-//   GT    group test over the candidates (insignificant coefficients at or
-//         after the cursor c),
-//   SCAN  next candidate's plane bit, the first 1 is the target,
-//   SIGN  the target's sign; it becomes significant and c moves past it.
-// One work mask W holds the coefficients still to visit in REF (significant
-// ones) and in SCAN (candidates).  The transitions that consume no bit (end
-// of refinement, no candidate left, next plane) need at most one settle step,
-// and every update is a select, so the loop body has a single branch (around
-// the LDS update).  Lanes decoding different blocks stay in lockstep: a wave
-// takes about as many iterations as one block has bits.
-enum : uint32_t { M_REF = 0, M_GT = 1, M_SCAN = 2, M_SIGN = 3, M_DONE = 4 };
-
-// Mode transitions, one nibble per (mode, bit, W exhausted) at index
-// mode*4 + bit*2 + exhausted: low 3 bits the next mode, bit 3 "next plane".
-//   REF:  W left -> REF; W exhausted -> GT (group test from cursor 0)
-//   GT:   bit 0 -> next plane; bit 1 -> SCAN
-//   SCAN: bit 1 -> SIGN; bit 0 with candidates left -> SCAN; none left -> DONE
-//   SIGN: -> GT
-static constexpr uint64_t mode_table() {
-    uint64_t t = 0;
-    const uint32_t e[16] = {M_REF, M_GT, M_REF, M_GT,            // REF
-                            M_GT | 8u, M_GT | 8u, M_SCAN, M_SCAN, // GT
-                            M_SCAN, M_DONE, M_SIGN, M_SIGN,       // SCAN
-                            M_GT, M_GT, M_GT, M_GT};              // SIGN
-    for (int i = 0; i < 16; ++i) t |= (uint64_t)e[i] << (4 * i);
-    return t;
-}
-static constexpr uint64_t kModeTable = mode_table();
-
-template <int RWMAX>
-__device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, int rate, DecodeLds<RWMAX> &L,
-                                              uint32_t lane, int32_t (&q)[64], int &e_out) {
-    const uint32_t rw = 2u * (uint32_t)rate;
-    const uint32_t w0 = rec[0];
-    if (!(w0 & 1u)) return false;
-#pragma unroll
-    for (int j = 1; j < RWMAX + 2; ++j) L.rec[j * 64 + lane] = (uint32_t)j < rw ? rec[j] : 0u;
-#pragma unroll
-    for (int j = 0; j < 64; ++j) L.mag[j * 64 + lane] = 0u;
-    e_out = (int)((w0 >> 1) & 0xFFu) - 127;
-    const uint32_t B = 64u * (uint32_t)rate;
-    // buf holds nbits >= 32 unread bits; refills take the next word when it
-    // drops below 32; at most rw - 1 refills happen before pos reaches B, so
-    // wi stays <= rw + 1 <= RWMAX + 1
-    uint64_t buf = ((uint64_t)w0 | ((uint64_t)L.rec[64 + lane] << 32)) >> 9;
-    uint32_t nbits = 55, wi = 2, pos = 9;
-    uint32_t nxt = L.rec[2 * 64 + lane];
-    uint64_t S = 0, NEG = 0, W = 0;
-    uint32_t c = 0, t = 0;
-    int k = 29;
-    uint32_t mode = M_GT;   // plane 29 has nothing to refine; every coefficient is a candidate
-    while (mode != M_DONE && pos < B) {
-        const uint32_t bit = (uint32_t)buf & 1u;
-        buf >>= 1;
-        --nbits;
-        ++pos;
-        if (nbits < 32u) {   // wave-uniform: every active lane has consumed the same bit count
-            buf |= (uint64_t)nxt << nbits;
-            nbits += 32u;
-            ++wi;
-            nxt = L.rec[wi * 64 + lane];
-        }
-
-        const bool isREF = mode == M_REF, isGT = mode == M_GT, isSCAN = mode == M_SCAN, isSIGN = mode == M_SIGN;
-        const uint32_t j = (uint32_t)__builtin_ctzll(W | (1ull << 63));   // W != 0 in REF and SCAN
-        const uint64_t Wn = W & (W - 1ull);
-        // refinement bit (REF) or the new coefficient's top bit (SIGN); other
-        // modes OR 0, so every lane issues the same LDS instruction
-        const uint32_t at = isREF ? j : t;
-        const uint32_t v = (isREF ? bit : (isSIGN ? 1u : 0u)) << k;
-        __hip_atomic_fetch_or(&L.mag[at * 64 + lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        const uint64_t tbit = 1ull << t;
-        S |= isSIGN ? tbit : 0ull;
-        NEG |= (isSIGN && bit) ? tbit : 0ull;
-        c = isSIGN ? t + 1u : (isREF ? 0u : c);   // REF ends into a group test from cursor 0
-        const uint64_t cand = c >= 64u ? 0ull : (~S & (~0ull << c));
-        t = (isSCAN && bit) ? j : t;
-        // next mode from (mode, bit, W exhausted): nibble = mode | next-plane << 3
-        const uint32_t idx = mode * 4u + bit * 2u + (Wn == 0ull ? 1u : 0u);
-        const uint32_t e = (uint32_t)(kModeTable >> (idx * 4u)) & 15u;
-        uint32_t nm = e & 7u;
-        // settle: a group test with no candidate left ends the plane
-        const bool np = (e >> 3) != 0u || (nm == M_GT && cand == 0ull);
-        W = isGT ? cand : Wn;   // a group test that hits scans the candidates
-        const int kn = np ? k - 1 : k;
-        W = np ? S : W;
-        c = np ? 0u : c;
-        nm = np ? (kn < 0 ? M_DONE : (S != 0ull ? M_REF : M_GT)) : nm;
-        k = kn;
-        mode = nm;
-    }
-#pragma unroll
-    for (int j = 0; j < 64; ++j) {
-        int32_t v = (int32_t)L.mag[j * 64 + lane];   // magnitudes are below 2^30; 0 if never significant
-        if ((NEG >> j) & 1ull) v = -v;
-        q[kOrder.ord[j]] = v;
-    }
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-        for (int x = 0; x < 4; ++x) inv4(q[x + 4 * y], q[x + 4 * y + 16], q[x + 4 * y + 32], q[x + 4 * y + 48]);
-#pragma unroll
-    for (int z = 0; z < 4; ++z)
-#pragma unroll
-        for (int x = 0; x < 4; ++x) inv4(q[x + 16 * z], q[x + 16 * z + 4], q[x + 16 * z + 8], q[x + 16 * z + 12]);
-#pragma unroll
-    for (int z = 0; z < 4; ++z)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) inv4(q[4 * y + 16 * z], q[4 * y + 16 * z + 1], q[4 * y + 16 * z + 2], q[4 * y + 16 * z + 3]);
-    return true;
-}
 
 // Decode one block to 64 floats, stored with 16-byte stores to dst (raster order).
 template <int RWMAX>
