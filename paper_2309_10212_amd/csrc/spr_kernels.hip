@@ -398,7 +398,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         AxisWalk wb;   // block-level walk state, valid while bvalid
         AxisWalk wc;   // coarse-level walk state, valid while cvalid
         double tcur;
-        bool bvalid, ctest, cvalid = false;
+        bool bvalid, cvalid = false;
         bool alive = true;
         uint32_t found = 0;
         if (state == RAY_NOT_STARTED) {
@@ -406,7 +406,6 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
 #pragma unroll
             for (int a = 0; a < 3; ++a) cc[a] = cell_at(R, LC, a, tcur, 0, tchi[a]);
             bvalid = false;
-            ctest = true;
         } else {
             uint32_t b = state;
             cb[0] = (int)(b % (uint32_t)u.nb[0]);
@@ -417,33 +416,24 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
             if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) alive = false;
             tcur = tn;
             bvalid = true;
-            ctest = true;   // (re)load the coarse cell's block bits
 #pragma unroll
             for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
         }
         uint32_t nbuf = 0, flushed = 0;   // candidates staged in LDS / already written
-        uint64_t cm = 0;
-        const int max_steps = u.tb[0] + u.tb[1] + u.tb[2] + u.tc[0] + u.tc[1] + u.tc[2] + 8;
+        const int max_steps = u.tb[0] + u.tb[1] + u.tb[2] + u.tc[0] + u.tc[1] + u.tc[2] + 16;
         int steps = 0;
+        // Outer loop: one coarse cell per iteration (its mask and distance are
+        // loaded here, once for the whole wave); an empty cell is left by a
+        // jump or a coarse step.  Inner loop: the blocks of a nonempty coarse
+        // cell, no memory access but the LDS staging.
         while (alive && found < ns) {
             if (++steps > max_steps) { alive = false; break; }   // every step advances an index
-            if (ctest) {
-                const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
-                cm = cmask[cid];
-                const int cd = cdist[cid];
-                if (cm != 0) {
-                    if (!bvalid) {
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            int lo = 4 * cc[a], hi = 4 * cc[a] + 3;
-                            if (hi > tbhi[a]) hi = tbhi[a];
-                            cb[a] = cell_at(R, LB, a, tcur, lo, hi);
-                        }
-                        walk_init(R, LB, cb, wb);
-                        bvalid = true;
-                    }
-                    ctest = false;
-                } else if (cd >= 2) {
+            const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
+            const uint64_t cm = cmask[cid];
+            const int cd = cdist[cid];
+            if (cm == 0) {
+                bvalid = false;
+                if (cd >= 2) {
                     // every coarse cell within cd-1 (chessboard) is empty: leave that box
                     // in one jump.  t* = the first crossing of one of its faces (or of
                     // the domain) - the parameter at which a cell-by-cell walk leaves
@@ -467,9 +457,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
 #pragma unroll
                     for (int a = 0; a < 3; ++a) cc[a] = cell_at(R, LC, a, tn, 0, tchi[a]);
                     tcur = tn;
-                    bvalid = false;
                     cvalid = false;
-                    continue;
                 } else {
                     // empty coarse cell: step over it at the coarse level
                     if (!cvalid) {
@@ -479,30 +467,42 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                     double tn = walk_exit(wc);
                     if (tn > R.tx || !walk_step(R, LC, wc, cc, tn, zero3, tchi)) { alive = false; break; }
                     tcur = tn;
-                    bvalid = false;
-                    continue;
                 }
+                continue;
             }
-            const bool emit = (cm >> local_bit(cb)) & 1ull;
-            if (emit) {
-                const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * u.nb[1] + cb[1]) * u.nb[0] + cb[0]);
-                s_slot[nbuf][threadIdx.x] = bid;
-                found++;
-                if (++nbuf == TR_BUF) {
-                    for (uint32_t k = 0; k < TR_BUF; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
-                    flushed += TR_BUF;
-                    nbuf = 0;
-                }
-                if (found == ns) break;
-            }
-            double tn = walk_exit(wb);
-            if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) { alive = false; break; }
-            tcur = tn;
-            if ((cb[0] >> 2) != cc[0] || (cb[1] >> 2) != cc[1] || (cb[2] >> 2) != cc[2]) {
+            if (!bvalid) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
-                ctest = true;
-                cvalid = false;
+                for (int a = 0; a < 3; ++a) {
+                    int lo = 4 * cc[a], hi = 4 * cc[a] + 3;
+                    if (hi > tbhi[a]) hi = tbhi[a];
+                    cb[a] = cell_at(R, LB, a, tcur, lo, hi);
+                }
+                walk_init(R, LB, cb, wb);
+                bvalid = true;
+            }
+            cvalid = false;
+            while (true) {
+                const bool emit = (cm >> local_bit(cb)) & 1ull;
+                if (emit) {
+                    const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * u.nb[1] + cb[1]) * u.nb[0] + cb[0]);
+                    s_slot[nbuf][threadIdx.x] = bid;
+                    found++;
+                    if (++nbuf == TR_BUF) {
+                        for (uint32_t k = 0; k < TR_BUF; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
+                        flushed += TR_BUF;
+                        nbuf = 0;
+                    }
+                    if (found == ns) break;
+                }
+                if (++steps > max_steps) { alive = false; break; }
+                double tn = walk_exit(wb);
+                if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) { alive = false; break; }
+                tcur = tn;
+                if ((cb[0] >> 2) != cc[0] || (cb[1] >> 2) != cc[1] || (cb[2] >> 2) != cc[2]) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
+                    break;
+                }
             }
         }
         for (uint32_t k = 0; k < nbuf; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
