@@ -212,7 +212,7 @@ def main():
         log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
 
-    ctx.profile(not args.no_profile, reset=True)
+    # timed region: graph-replayed passes, no per-kernel events
     c0 = ctx.counters()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -221,15 +221,41 @@ def main():
         infos.append(step(args.warmup + i, args.spec_cap))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.profile(False)
     c1 = ctx.counters()
-    ktimes = ctx.kernel_times()
     dc = {k: c1[k] - c0[k] for k in c1}
     dc["max_active_blocks"] = c1["max_active_blocks"]
     nb_vol = ((n + 3) // 4) ** 3
     dc["load_blocks"] = nb_vol * args.steps
     dc["load_coarse"] = ((((n + 3) // 4) + 3) // 4) ** 3 * args.steps
     dc["setup_pixels"] = args.w * args.h * args.steps
+
+    # the same steps again with per-kernel HIP events (eager launches, an
+    # event pair around every kernel, on the library's stream), on a reloaded
+    # volume after the same warm-up, so that block-cache state and work match
+    ktimes, dcp, prof_ms = {}, dc, None
+    if not args.no_profile:
+        vol.free()
+        vol = ctx.load_volume(stream, (n, n, n), args.rate)
+        for i in range(args.warmup):
+            step(i, args.spec_cap)
+        ctx.profile(True, reset=True)
+        p0 = ctx.counters()
+        torch.cuda.synchronize()
+        q0 = time.perf_counter()
+        for i in range(args.steps):
+            step(args.warmup + i, args.spec_cap)
+        torch.cuda.synchronize()
+        q1 = time.perf_counter()
+        ctx.profile(False)
+        p1 = ctx.counters()
+        ktimes = ctx.kernel_times()
+        dcp = {k: p1[k] - p0[k] for k in p1}
+        for k in ("max_active_blocks", "load_blocks", "load_coarse", "setup_pixels"):
+            dcp[k] = dc[k]
+        prof_ms = (q1 - q0) * 1e3 / args.steps
+        if dcp["blocks_decoded"] != dc["blocks_decoded"] or dcp["pairs"] != dc["pairs"]:
+            log(f"[bench] note: the evented steps did other work (decoded {dcp['blocks_decoded']} vs "
+                f"{dc['blocks_decoded']}, pairs {dcp['pairs']} vs {dc['pairs']})")
     elapsed = t1 - t0
     rays = sum(i["rays_entered"] for i in infos)
     passes = sum(i["passes"] for i in infos)
@@ -243,11 +269,11 @@ def main():
 
     # roofline of the dominant kernel (largest device time in the timed
     # region: the load path, request set-up and every pass)
-    dom = max(ktimes.items(), key=lambda kv: kv[1][0])
+    dom = max(ktimes.items(), key=lambda kv: kv[1][0]) if ktimes else (None, (0.0, 0))
     log("[bench] device ms per step by kernel: " + ", ".join(
         f"{k} {ms / args.steps:.3f} ({nl})" for k, (ms, nl) in sorted(ktimes.items(), key=lambda kv: -kv[1][0])[:8]))
     dname, (dms, dn) = dom
-    byts = kernel_bytes(dname, dc, args.rate)
+    byts = kernel_bytes(dname, dcp, args.rate)
     roof = None
     if byts is not None and dn > 0 and dms > 0:
         per_launch = byts / dn
@@ -331,6 +357,7 @@ def main():
         "ms_per_pass": round(elapsed * 1e3 / max(passes, 1), 4),
         "device_ms_per_pass": round(dev_ms / max(passes, 1), 4),
         "device_ms_per_step": round(dev_ms_all / max(args.steps, 1), 4),
+        "evented_ms_per_step": round(prof_ms, 4) if prof_ms is not None else None,
         "passes_per_step": passes / args.steps,
         "blocks_decoded_per_s": round(dc["blocks_decoded"] / elapsed, 1),
         "blocks_decoded_per_decode_s": round(dc["blocks_decoded"] / (dec_ms / 1e3), 1) if dec_ms > 0 else None,
