@@ -260,7 +260,7 @@ def main():
     rays = sum(i["rays_entered"] for i in infos)
     passes = sum(i["passes"] for i in infos)
     value = rays / elapsed
-    PASS_KERNELS = ("k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_alloc_plan", "k_evict_hist",
+    PASS_KERNELS = ("k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_evict_hist",
                     "k_evict", "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact")
     dev_ms_all = sum(ms for ms, _ in ktimes.values())
     # pass kernels only (the set-up pass also runs k_pass_begin/k_pass_end/k_compact once per step)

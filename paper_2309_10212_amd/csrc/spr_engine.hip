@@ -319,7 +319,7 @@ spr_status graph_pass(spr_ctx *c, const Table &T, const PassGrids &g, hipGraph_t
 }
 
 // Profiling: add one recorded event set's kernel intervals to their slots.
-constexpr int PASS_SLOTS[PASS_KERNELS] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13};
+constexpr int PASS_SLOTS[PASS_KERNELS] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12};
 
 spr_status prof_collect(spr_ctx *c, spr_ctx::ProfRec &rec) {
     if (!rec.pending) return SPR_OK;

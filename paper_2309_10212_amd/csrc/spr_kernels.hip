@@ -676,21 +676,23 @@ __global__ __launch_bounds__(256) void k_lookup(PassCtl *ctl, const VolDev *vols
 // ages (pass - stamp, clamped to 63) picks the largest age threshold whose
 // tail covers max(shortfall, n_slots/16) slots, and every slot at or above it
 // is evicted in one sweep.
-__global__ void k_alloc_plan(PassCtl *ctl) {
-    if (threadIdx.x != 0) return;
-    ctl->served = ctl->cursor;   // the admitted blocks' runs cover exactly the served pairs
-    uint32_t m = ctl->n_miss, f = ctl->free_top;
-    if (m > f) {
-        uint32_t short_by = m - f;
-        uint32_t batch = ctl->n_slots / 16u;
-        ctl->need = short_by > batch ? short_by : batch;
-    } else {
-        ctl->need = 0;
-    }
-}
-
+// Allocation plan, then (only when the free slots run short) the age
+// histogram of the slots not used this pass.  Every workgroup computes the
+// plan from the counters, which are final here; workgroup 0 publishes it.
+// The admitted blocks' runs cover exactly the served pairs; eviction frees at
+// least the shortfall, in batches of n_slots/16.
 __global__ __launch_bounds__(256) void k_evict_hist(PassCtl *ctl, Cache C) {
-    if (ctl->need == 0) return;
+    const uint32_t m = ctl->n_miss, f = ctl->free_top;
+    uint32_t need = 0;
+    if (m > f) {
+        const uint32_t short_by = m - f, batch = ctl->n_slots / 16u;
+        need = short_by > batch ? short_by : batch;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->served = ctl->cursor;
+        ctl->need = need;
+    }
+    if (need == 0) return;
     __shared__ uint32_t h[64];
     if (threadIdx.x < 64) h[threadIdx.x] = 0;
     __syncthreads();
@@ -710,7 +712,7 @@ __global__ __launch_bounds__(256) void k_evict_hist(PassCtl *ctl, Cache C) {
     __syncthreads();
     if (last && threadIdx.x == 0) {
         __threadfence();
-        uint32_t need = ctl->need, acc = 0, T = 1;
+        uint32_t acc = 0, T = 1;
         for (int a = 63; a >= 1; --a) {
             acc += __hip_atomic_load(&ctl->hist[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (acc >= need) { T = (uint32_t)a; break; }
@@ -1284,11 +1286,11 @@ hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const V
 }
 
 const char *const PASS_KERNEL_NAMES[PASS_KERNELS] = {
-    "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_alloc_plan", "k_evict_hist", "k_evict",
+    "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_evict_hist", "k_evict",
     "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact"};
 
 const char *const PROF_NAMES[PROF_SLOTS] = {
-    "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_alloc_plan", "k_evict_hist", "k_evict",
+    "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_evict_hist", "k_evict",
     "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact",
     "k_block_ranges", "k_fine_grid", "k_coarse_grid", "k_iso_masks", "k_init_rays"};
 
@@ -1304,7 +1306,6 @@ hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev
     mark(); hipLaunchKernelGGL(k_dedupe, dim3(g.dedupe), dim3(256), 0, s, ctl, T, vols, W);
     mark(); hipLaunchKernelGGL(k_mark, dim3(g.pairs), dim3(256), 0, s, ctl, vols, W);
     mark(); hipLaunchKernelGGL(k_lookup, dim3(g.blocks), dim3(256), 0, s, ctl, vols, W, C);
-    mark(); hipLaunchKernelGGL(k_alloc_plan, dim3(1), dim3(64), 0, s, ctl);
     mark(); hipLaunchKernelGGL(k_evict_hist, dim3(g.slots), dim3(256), 0, s, ctl, C);
     mark(); hipLaunchKernelGGL(k_evict, dim3(g.slots), dim3(256), 0, s, ctl, vols, C);
     mark(); hipLaunchKernelGGL(k_assign_scatter, dim3(g.assign + g.scatter), dim3(256), 0, s, ctl, T, vols, W, C, g.assign);
