@@ -244,12 +244,13 @@ spr_status ensure_work(spr_ctx *c, uint64_t P) {
     dfree(c, W.vis_list, oP); dfree(c, W.vis_off, oP);
     dfree(c, W.act_list, oK); dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
     dfree(c, W.pair_rank, oP); dfree(c, W.s_ray, oP); dfree(c, W.s_q, oP); dfree(c, W.s_vi, oP);
+    dfree(c, W.vis_nsl, 8 * oP);
     W.cap_P = 0; W.cap_K = 0;
     uint64_t cP = P, cK = 8 * P;
     CHK(dalloc(c, cP, &W.vis_list)); CHK(dalloc(c, cP, &W.vis_off));
     CHK(dalloc(c, cK, &W.act_list)); CHK(dalloc(c, cK, &W.miss_list)); CHK(dalloc(c, cK, &W.miss_slot));
     CHK(dalloc(c, cP, &W.pair_rank)); CHK(dalloc(c, cP, &W.s_ray)); CHK(dalloc(c, cP, &W.s_q));
-    CHK(dalloc(c, cP, &W.s_vi));
+    CHK(dalloc(c, cP, &W.s_vi)); CHK(dalloc(c, 8 * cP, &W.vis_nsl));
     W.cap_P = (uint32_t)cP;
     W.cap_K = (uint32_t)cK;
     c->work_gen++;

@@ -149,6 +149,7 @@ struct Work {
     uint32_t *s_ray;            // sorted pairs: (req << 24) | pixel
     uint32_t *s_q;              // sorted pairs: pair slot within the request
     uint32_t *s_vi;             // sorted pairs: visible-list index
+    uint32_t *vis_nsl;          // per visible block: slots of its 2x2x2 block neighbourhood (8, NONE outside)
     uint32_t cap_P;             // pairs capacity
     uint32_t cap_K;             // active/miss list capacity
 };

@@ -812,6 +812,31 @@ __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols,
         const uint32_t *rec = V.stream + (uint64_t)(uint32_t)e * (uint64_t)V.rec_words;
         decode_to<32>(rec, V.rate, L, threadIdx.x, C.slots + (size_t)W.miss_slot[i] * 64);
     }
+    // Per admitted visible block, the slots of its 2x2x2 neighbourhood (every
+    // neighbour is active, so it holds a slot by now): the raytrace reads them
+    // with the visible-list entry instead of eight map lookups after it.  The
+    // entries go to the workgroups from the end of the grid, which have no
+    // misses to decode unless the miss list is long.
+    const uint32_t vadm = admitted_blocks(ctl);
+    const uint32_t wr = gridDim.x - 1u - blockIdx.x;
+    for (uint32_t v = wr * 64 + threadIdx.x; v < vadm; v += gridDim.x * 64) {
+        const uint64_t e = W.vis_list[v];
+        const VolDev &V = vols[(uint32_t)(e >> 32)];
+        const uint32_t b = (uint32_t)e;
+        const int bx = (int)(b % (uint32_t)V.nb[0]);
+        const int by = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
+        const int bz = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
+        uint32_t nsl[8];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
+            const bool ok = x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2];
+            nsl[o] = ok ? V.map[((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2] : NONE;
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(W.vis_nsl + (size_t)v * 8);
+        dst[0] = make_uint4(nsl[0], nsl[1], nsl[2], nsl[3]);
+        dst[1] = make_uint4(nsl[4], nsl[5], nsl[6], nsl[7]);
+    }
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->free_top -= m;   // the assigned slots leave the free stack
 }
@@ -871,37 +896,46 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
         }
         const uint32_t nloc = tot < (uint32_t)RT_LB ? tot : (uint32_t)RT_LB;
         if (start && lb < (uint32_t)RT_LB) {
-            uint64_t e = W.vis_list[vi];
+            const uint64_t e = W.vis_list[vi];
+            const uint4 n0 = reinterpret_cast<const uint4 *>(W.vis_nsl + (size_t)vi * 8)[0];
+            const uint4 n1 = reinterpret_cast<const uint4 *>(W.vis_nsl + (size_t)vi * 8)[1];
             const VolDev &V = vols[(uint32_t)(e >> 32)];
             uint32_t b = (uint32_t)e;
             s_bb[lb][0] = (int)(b % (uint32_t)V.nb[0]);
             s_bb[lb][1] = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
             s_bb[lb][2] = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
             s_bb[lb][3] = (int)(uint32_t)(e >> 32);
+            s_nsl[lb][0] = n0.x; s_nsl[lb][1] = n0.y; s_nsl[lb][2] = n0.z; s_nsl[lb][3] = n0.w;
+            s_nsl[lb][4] = n1.x; s_nsl[lb][5] = n1.y; s_nsl[lb][6] = n1.z; s_nsl[lb][7] = n1.w;
         }
         __syncthreads();
-        // slots of the 8 blocks of each staged block's 2x2x2 neighbourhood
-        for (uint32_t x = tid; x < nloc * 8; x += RT_TILE) {
-            uint32_t l = x >> 3, o = x & 7;
-            const VolDev &V = vols[s_bb[l][3]];
-            int x2 = s_bb[l][0] + (o & 1), y2 = s_bb[l][1] + ((o >> 1) & 1), z2 = s_bb[l][2] + (o >> 2);
-            bool ok = x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2];
-            s_nsl[l][o] = ok ? V.map[((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2] : NONE;
-        }
-        __syncthreads();
-        // stage the 5^3 dual grids
-        for (uint32_t x = tid; x < nloc * 125; x += RT_TILE) {
-            uint32_t l = x / 125, k = x - l * 125;
-            int lx = (int)(k % 5), ly = (int)((k / 5) % 5), lz = (int)(k / 25);
-            int o = (lx >> 2) | ((ly >> 2) << 1) | ((lz >> 2) << 2);
-            uint32_t sl = s_nsl[l][o];
-            s_grid[l][k] = sl == NONE ? 0.0f : C.slots[(size_t)sl * 64 + ((lx & 3) + 4 * (ly & 3) + 16 * (lz & 3))];
+        // stage the 5^3 dual grids, four loads in flight per thread before
+        // their LDS stores
+        for (uint32_t x0 = tid; x0 < nloc * 125; x0 += 4 * RT_TILE) {
+            float sv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t x = x0 + (uint32_t)u * RT_TILE;
+                sv[u] = 0.0f;
+                if (x < nloc * 125) {
+                    const uint32_t l = x / 125, k = x - l * 125;
+                    const int lx = (int)(k % 5), ly = (int)((k / 5) % 5), lz = (int)(k / 25);
+                    const int o = (lx >> 2) | ((ly >> 2) << 1) | ((lz >> 2) << 2);
+                    const uint32_t sl = s_nsl[l][o];
+                    if (sl != NONE) sv[u] = C.slots[(size_t)sl * 64 + ((lx & 3) + 4 * (ly & 3) + 16 * (lz & 3))];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t x = x0 + (uint32_t)u * RT_TILE;
+                if (x < nloc * 125) s_grid[x / 125][x % 125] = sv[u];
+            }
         }
         __syncthreads();
         if (valid) {
-            uint32_t ray = W.s_ray[j];
-            uint32_t r = ray >> 24, pix = ray & 0xFFFFFFu;
-            uint32_t qq = W.s_q[j];
+            const uint32_t ray = W.s_ray[j];
+            const uint32_t r = ray >> 24, pix = ray & 0xFFFFFFu;
+            const uint32_t qq = W.s_q[j];
             const ReqDev &q = T.reqs[r];
             const VolDev &V = vols[q.vol];
             int bb[3];
@@ -915,11 +949,7 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
                 bb[1] = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
                 bb[2] = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
 #pragma unroll
-                for (int o = 0; o < 8; ++o) {
-                    int x2 = bb[0] + (o & 1), y2 = bb[1] + ((o >> 1) & 1), z2 = bb[2] + (o >> 2);
-                    bool ok = x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2];
-                    nsl[o] = ok ? V.map[((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2] : NONE;
-                }
+                for (int o = 0; o < 8; ++o) nsl[o] = W.vis_nsl[(size_t)vi * 8 + o];
             }
             Ray R;
             make_ray(q, V.n, pix, R);
