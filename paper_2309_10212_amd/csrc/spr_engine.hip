@@ -264,6 +264,7 @@ spr_status alloc_table(spr_ctx *c, uint32_t cap, uint64_t max_A, uint64_t max_P,
     CHK(dalloc(c, 1, &T.hdr));
     CHK(dalloc(c, cap + 1, &T.act_base));
     CHK(dalloc(c, cap + 1, &T.pair_base));
+    CHK(dalloc(c, cap + 1, &T.trav_base));
     CHK(dalloc(c, max_A / 64 + 2, &T.wave_rec));
     CHK(dalloc(c, max_A / 64 + 2, &T.wave_off));
     return SPR_OK;
@@ -273,6 +274,7 @@ void free_table(spr_ctx *c, Table &T) {
     dfree(c, T.hdr, 1);
     dfree(c, T.act_base, T.cap + 1);
     dfree(c, T.pair_base, T.cap + 1);
+    dfree(c, T.trav_base, T.cap + 1);
     dfree(c, T.wave_rec, T.max_A / 64 + 2);
     dfree(c, T.wave_off, T.max_A / 64 + 2);
 }

@@ -61,7 +61,8 @@ struct ReqState {
     uint32_t n_act_prev;        // active rays at the start of the last pass
     uint32_t last_pairs, last_deferred, last_terminated, last_nspec;
     uint32_t entered;           // rays that entered the volume (set at the first pass)
-    uint32_t pad[2];
+    uint32_t segs;              // traversal lanes per active ray this pass (power of two, <= 16)
+    uint32_t pad[1];
     unsigned long long tot_pairs;
     unsigned long long bcmc;    // blocks whose fine range contains the isovalue (set up with the masks)
 };
@@ -116,7 +117,8 @@ struct PassCtl {
     uint32_t overflow;          // set if the slot supply ever fell short (never by construction)
     uint32_t assigned;          // misses that received a slot this pass
     uint32_t rays;              // active rays of this pass (unpadded)
-    uint32_t pad[8];
+    uint32_t A_trav;            // traversal lane space of this pass (64-padded per request)
+    uint32_t pad[7];
     uint32_t hist[64];
     // cumulative counters since context creation
     unsigned long long acc_passes, acc_decoded, acc_visible, acc_active, acc_pairs, acc_evicted, acc_overflow,
@@ -130,6 +132,7 @@ struct Table {
                                 // so membership can change between graph replays)
     uint32_t *act_base;         // cap+1, 64-aligned prefix of n_act
     uint32_t *pair_base;        // cap+1, prefix of n_act*n_spec
+    uint32_t *trav_base;        // cap+1, 64-aligned prefix of n_act*segs (traversal lanes)
     uint4 *wave_rec;            // per 64-entry wave of the A space: survivors, pairs,
                                 // deferred pairs, terminated rays
     uint32_t *wave_off;         // exclusive prefix of the survivors

@@ -206,6 +206,15 @@ __device__ __forceinline__ uint32_t wave_bump(uint32_t *counter, uint32_t val) {
 
 // ---------------------------------------------------------------- K0 ------
 // Pass set-up: new pass stamp, counters cleared, per-request index spaces.
+// Candidates are staged in LDS and written out after the walk (or when
+// TR_BUF have accumulated): on this architecture one counter tracks vector
+// loads and stores alike, so a store inside the walk would make the next
+// mask load wait for the store's completion as well.
+constexpr uint32_t TR_BUF = 16;
+// A request with few active rays walks each ray on several lanes (segments
+// of its remaining parameter range), up to this many traversal lanes.
+constexpr uint32_t SEG_TARGET = 262144;
+
 __global__ void k_pass_begin(PassCtl *ctl, Table T, int is_init) {
     if (threadIdx.x < 64) ctl->hist[threadIdx.x] = 0;
     if (threadIdx.x != 0) return;
@@ -214,10 +223,25 @@ __global__ void k_pass_begin(PassCtl *ctl, Table T, int is_init) {
     ctl->cursor = 0; ctl->served = 0; ctl->deferred = 0; ctl->need = 0; ctl->evict_T = 64;
     ctl->evict_done_blocks = 0; ctl->evicted = 0; ctl->terminated = 0; ctl->pairs = 0; ctl->overflow = 0;
     const uint32_t nreq = T.hdr[0];
-    uint32_t A = 0, P = 0, rays = 0;
+    uint32_t A = 0, P = 0, rays = 0, AT = 0;
+    // traversal lanes per ray: a power of two up to 16 while the pass stays
+    // within SEG_TARGET lanes over all requests; only for requests whose
+    // slots fit one lane's staging buffer (the lanes' lists are merged after
+    // the walk)
+    uint32_t all_na = 0;
+    for (uint32_t r = 0; r < nreq; ++r) all_na += T.reqs[r].st->n_act;
+    uint32_t segs_all = 1;
+    if (!is_init && all_na > 0) {
+        const uint32_t want = SEG_TARGET / all_na;
+        while (segs_all < 16u && 2u * segs_all <= want) segs_all *= 2u;
+    }
     for (uint32_t r = 0; r < nreq; ++r) {
         ReqState *st = T.reqs[r].st;
         uint32_t na = st->n_act, ns = st->n_spec;
+        const uint32_t segs = (na > 0 && ns <= TR_BUF) ? segs_all : 1u;
+        st->segs = segs;
+        T.trav_base[r] = AT;
+        AT += round64(na * segs);
         T.act_base[r] = A;
         T.pair_base[r] = P;
         st->n_act_prev = na;
@@ -234,6 +258,8 @@ __global__ void k_pass_begin(PassCtl *ctl, Table T, int is_init) {
     ctl->rays = rays;
     T.act_base[nreq] = A;
     T.pair_base[nreq] = P;
+    T.trav_base[nreq] = AT;
+    ctl->A_trav = AT;
     ctl->A = A;
     ctl->P = P;
     ctl->nreq = nreq;
@@ -362,23 +388,22 @@ __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
 
 __device__ __forceinline__ bool range_has(float2 r, float iso) { return r.x <= iso && iso <= r.y; }
 
-// Candidates are staged in LDS and written out after the walk (or when
-// TR_BUF have accumulated): on this architecture one counter tracks vector
-// loads and stores alike, so a store inside the walk would make the next
-// mask load wait for the store's completion as well.
-constexpr uint32_t TR_BUF = 16;
 
 __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const VolDev *vols) {
     __shared__ uint32_t s_slot[TR_BUF][256];
-    const uint32_t A = ctl->A;
+    const uint32_t AT = ctl->A_trav;
     const uint32_t nreq = ctl->nreq;
-    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
-        // all lanes of a wave share a request (the A space is 64-aligned per request)
-        const uint32_t r = uni(find_req(T.act_base, nreq, p));
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < AT; p += gridDim.x * blockDim.x) {
+        // all lanes of a wave share a request (the lane space is 64-aligned per
+        // request); ray i of the request runs on lanes i*L .. i*L+L-1
+        const uint32_t r = uni(find_req(T.trav_base, nreq, p));
         const ReqDev &q = T.reqs[r];
         const ReqState *st = uni(q.st);
-        const uint32_t i = p - uni(T.act_base[r]);
-        if (i >= uni(st->n_act_prev)) continue;
+        const uint32_t L = uni(st->segs);
+        const uint32_t local = p - uni(T.trav_base[r]);
+        const uint32_t i = local >> __builtin_ctz(L);
+        const uint32_t seg = local & (L - 1u);
+        if (i >= uni(st->n_act_prev)) continue;   // whole segment groups only
         const uint32_t ns = uni(st->last_nspec);
         const uint32_t pix = uni(q.act[uni(st->cur)])[i];
         WaveReq u;
@@ -419,6 +444,31 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
 #pragma unroll
             for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
         }
+        // Segments (L > 1): the rest of the ray, [t_start, t_exit], is cut at
+        // t_k = t_start + (t_exit - t_start) k / L; lane k lists the blocks whose
+        // entry parameter lies in [t_k, t_k+1) (the first lane everything below
+        // t_1, the last everything from t_L-1 on), so every block the serial
+        // walk visits belongs to exactly one lane.  Lane k > 0 starts where the
+        // serial walk is at t_k: every plane with parameter <= t_k crossed
+        // (cell_at), and the block found there counts only if it was entered at
+        // t_k or later.
+        double t_lo = -__builtin_inf(), t_hi = __builtin_inf();
+        bool fresh = false;   // the next block found by cell_at needs its own entry parameter
+        if (L > 1u && alive) {
+            const double t0 = tcur, span = R.tx - tcur;
+            if (seg + 1u < L) t_hi = t0 + span * (double)(seg + 1u) / (double)L;
+            if (seg > 0u) {
+                t_lo = t0 + span * (double)seg / (double)L;
+                tcur = t_lo;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) cc[a] = cell_at(R, LC, a, tcur, 0, tchi[a]);
+                bvalid = false;
+                cvalid = false;
+                fresh = true;
+            }
+        }
+        double tau = tcur;    // entry parameter of the current block
+        bool seg_done = false;
         uint32_t nbuf = 0, flushed = 0;   // candidates staged in LDS / already written
         const int max_steps = u.tb[0] + u.tb[1] + u.tb[2] + u.tc[0] + u.tc[1] + u.tc[2] + 16;
         int steps = 0;
@@ -428,11 +478,13 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         // cell, no memory access but the LDS staging.
         while (alive && found < ns) {
             if (++steps > max_steps) { alive = false; break; }   // every step advances an index
+            if (tcur >= t_hi && !fresh) { seg_done = true; break; }   // the rest is the next lane's
             const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
             const uint64_t cm = cmask[cid];
             const int cd = cdist[cid];
             if (cm == 0) {
                 bvalid = false;
+                fresh = false;   // the walk moves on to plane crossings
                 if (cd >= 2) {
                     // every coarse cell within cd-1 (chessboard) is empty: leave that box
                     // in one jump.  t* = the first crossing of one of its faces (or of
@@ -479,15 +531,18 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                 }
                 walk_init(R, LB, cb, wb);
                 bvalid = true;
+                tau = fresh ? cell_entry(R, LB, cb) : tcur;
+                fresh = false;
             }
             cvalid = false;
             while (true) {
-                const bool emit = (cm >> local_bit(cb)) & 1ull;
+                if (tau >= t_hi) { seg_done = true; break; }
+                const bool emit = tau >= t_lo && ((cm >> local_bit(cb)) & 1ull);
                 if (emit) {
                     const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * u.nb[1] + cb[1]) * u.nb[0] + cb[0]);
                     s_slot[nbuf][threadIdx.x] = bid;
                     found++;
-                    if (++nbuf == TR_BUF) {
+                    if (++nbuf == TR_BUF && L == 1u) {   // segmented rays keep ns <= TR_BUF in LDS
                         for (uint32_t k = 0; k < TR_BUF; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
                         flushed += TR_BUF;
                         nbuf = 0;
@@ -498,19 +553,39 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                 double tn = walk_exit(wb);
                 if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) { alive = false; break; }
                 tcur = tn;
+                tau = tn;
                 if ((cb[0] >> 2) != cc[0] || (cb[1] >> 2) != cc[1] || (cb[2] >> 2) != cc[2]) {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
                     break;
                 }
             }
+            if (seg_done) break;
         }
-        for (uint32_t k = 0; k < nbuf; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
-        for (uint32_t k = found; k < ns; ++k) slots[k] = NONE;
         // The block of pair 0 (the first active ray's first candidate) takes
         // visible-list index 0, so it is always admitted and every pass makes
         // progress under the cache-capacity rule: reserve that index.
-        if (found > 0 && T.pair_base[r] + i * ns == 0) ctl->n_vis = 1u;
+        if (L == 1u) {
+            for (uint32_t k = 0; k < nbuf; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
+            for (uint32_t k = found; k < ns; ++k) slots[k] = NONE;
+            if (found > 0 && T.pair_base[r] + i * ns == 0) ctl->n_vis = 1u;
+        } else {
+            // merge the lanes' lists in segment order: lane k's candidates go
+            // after those of lanes 0..k-1; the first ns are the ray's slots
+            uint32_t incl = found;
+            for (uint32_t d = 1; d < L; d <<= 1) {
+                const uint32_t o = (uint32_t)__shfl_up((int)incl, d, (int)L);
+                if (seg >= d) incl += o;
+            }
+            const uint32_t before = incl - found;
+            const uint32_t total = (uint32_t)__shfl((int)incl, (int)(L - 1u), (int)L);
+            for (uint32_t k = 0; k < found; ++k)
+                if (before + k < ns) slots[before + k] = s_slot[k][threadIdx.x];
+            if (seg == 0u) {
+                for (uint32_t k = total < ns ? total : ns; k < ns; ++k) slots[k] = NONE;
+                if (total > 0 && T.pair_base[r] + i * ns == 0) ctl->n_vis = 1u;
+            }
+        }
     }
 }
 
