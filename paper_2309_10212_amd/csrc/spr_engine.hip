@@ -891,14 +891,18 @@ spr_status spr_render_run(spr_render *r, uint32_t max_passes, uint32_t *passes_r
     const uint32_t start = s0.passes;
     // Keep two passes in flight: after enqueuing pass i+1, wait for pass i's
     // copy of N_act.  A pass on a finished render does no work, so the one
-    // pass that may run past completion costs only its empty launches.
+    // pass that may run past completion costs only its empty launches; once
+    // the last N_act seen is small (the render is about to finish), keep one
+    // pass in flight, which trades that empty pass for one host round trip.
     const int DEPTH = 2;
+    const uint32_t NEAR_END = r->npix / 256u > 256u ? r->npix / 256u : 256u;
     hipEvent_t ev[DEPTH] = {c->ev0, c->ev1};
     volatile uint32_t *flag = (volatile uint32_t *)((char *)c->pinned + 3840);   // clear of the other staging areas
-    uint32_t enq = 0, waited = 0;
+    uint32_t enq = 0, waited = 0, last_act = s0.n_act;
     bool done = s0.n_act == 0;
     while (!done) {
-        while (enq < max_passes && enq - waited < (uint32_t)DEPTH) {
+        const uint32_t depth = last_act <= NEAR_END ? 1u : (uint32_t)DEPTH;
+        while (enq < max_passes && enq - waited < depth) {
             CHK(spr_render_pass(r, nullptr));
             HIPCHK(hipMemcpyAsync((void *)(flag + (enq % DEPTH)), &r->d_st->n_act, 4, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipEventRecord(ev[enq % DEPTH], c->stream));
@@ -906,7 +910,8 @@ spr_status spr_render_run(spr_render *r, uint32_t max_passes, uint32_t *passes_r
         }
         if (waited == enq) break;   // max_passes reached
         HIPCHK(hipEventSynchronize(ev[waited % DEPTH]));
-        done = flag[waited % DEPTH] == 0;
+        last_act = flag[waited % DEPTH];
+        done = last_act == 0;
         ++waited;
     }
     HIPCHK(hipStreamSynchronize(c->stream));
