@@ -201,17 +201,28 @@ __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, 
     for (uint32_t r = 0; r < nrun; ++r) {
         const uint32_t info = L.run[r * 64 + lane];
         const uint32_t ne = r + 1u < nrun ? (L.run[(r + 1u) * 64 + lane] >> 16) : nev;
-        uint64_t bits = rec_window(L.rec, lane, info & 1023u);
-        uint64_t D = 0, todo = Sr;
-        while (todo != 0ull) {
-            const uint32_t j = (uint32_t)__builtin_ctzll(todo);
-            todo &= todo - 1ull;
-            D |= (bits & 1ull) << j;
-            bits >>= 1;
+        const uint64_t bits = rec_window(L.rec, lane, info & 1023u);
+        // deposit, in 32-bit halves: the refinement bits of coefficients 32..63
+        // follow those of 0..31 (as many as the low half has significant ones)
+        uint32_t Dlo = 0, Dhi = 0;
+        uint32_t todo = (uint32_t)Sr, b32 = (uint32_t)bits;
+        while (todo != 0u) {
+            const uint32_t j = (uint32_t)__builtin_ctz(todo);
+            todo &= todo - 1u;
+            Dlo |= (b32 & 1u) << j;
+            b32 >>= 1;
+        }
+        todo = (uint32_t)(Sr >> 32);
+        b32 = (uint32_t)(bits >> __builtin_popcount((uint32_t)Sr));
+        while (todo != 0u) {
+            const uint32_t j = (uint32_t)__builtin_ctz(todo);
+            todo &= todo - 1u;
+            Dhi |= (b32 & 1u) << j;
+            b32 >>= 1;
         }
         uint64_t Sn = Sr;
         for (; e < ne; ++e) Sn |= 1ull << L.ev[e * 64 + lane];
-        or_plane(m, D | (Sn & ~Sr), (info >> 10) & 31u);
+        or_plane(m, ((uint64_t)Dhi << 32 | Dlo) | (Sn & ~Sr), (info >> 10) & 31u);
         Sr = Sn;
     }
 
