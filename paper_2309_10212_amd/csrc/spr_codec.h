@@ -120,13 +120,19 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t x, uint32_t r) {
     return b;
 }
 
-// m[j] |= bit j of D at plane k, for the 64 coefficients.
+// m[j] |= bit j of D at plane k, for the 64 coefficients.  A half that is
+// zero on every lane of the wave (the high coefficients of early planes)
+// is skipped: OR-ing zeros changes nothing.
 __device__ __forceinline__ void or_plane(uint32_t (&m)[64], uint64_t D, uint32_t k) {
     const uint32_t lo = (uint32_t)D, hi = (uint32_t)(D >> 32);
+    if (__ballot(lo != 0u) != 0ull) {
 #pragma unroll
-    for (int j = 0; j < 32; ++j) m[j] |= ((lo >> j) & 1u) << k;
+        for (int j = 0; j < 32; ++j) m[j] |= ((lo >> j) & 1u) << k;
+    }
+    if (__ballot(hi != 0u) != 0ull) {
 #pragma unroll
-    for (int j = 0; j < 32; ++j) m[32 + j] |= ((hi >> j) & 1u) << k;
+        for (int j = 0; j < 32; ++j) m[32 + j] |= ((hi >> j) & 1u) << k;
+    }
 }
 
 // Decodes the record into q[64] (raster order) and the block exponent.

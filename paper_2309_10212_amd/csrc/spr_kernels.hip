@@ -91,10 +91,15 @@ __global__ __launch_bounds__(64) void k_block_ranges(VolDev V, float2 *blk) {
             } else {
                 // conversion to float is monotone: reduce the integers, convert two
                 int32_t qlo = 0x7FFFFFFF, qhi = (int32_t)0x80000000;
+                if (ex >= 4 && ey >= 4 && ez >= 4) {   // interior block: every sample counts
 #pragma unroll
-                for (int i = 0; i < 64; ++i) {
-                    bool in = (i & 3) < ex && ((i >> 2) & 3) < ey && (i >> 4) < ez;
-                    if (in) { qlo = q[i] < qlo ? q[i] : qlo; qhi = q[i] > qhi ? q[i] : qhi; }
+                    for (int i = 0; i < 64; ++i) { qlo = q[i] < qlo ? q[i] : qlo; qhi = q[i] > qhi ? q[i] : qhi; }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 64; ++i) {
+                        bool in = (i & 3) < ex && ((i >> 2) & 3) < ey && (i >> 4) < ez;
+                        if (in) { qlo = q[i] < qlo ? q[i] : qlo; qhi = q[i] > qhi ? q[i] : qhi; }
+                    }
                 }
                 lo = (float)ldexp((double)qlo, e - 27);
                 hi = (float)ldexp((double)qhi, e - 27);
