@@ -1184,11 +1184,19 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
     const uint32_t w0 = t * per < nw ? t * per : nw;
     const uint32_t w1 = w0 + per < nw ? w0 + per : nw;
     uint32_t run = 0;
+    // up to PE_REG records per thread are loaded once, all at the start, and
+    // kept in registers (unrolled, so their indices are compile-time)
+    constexpr uint32_t PE_REG = 8;
+    const bool in_regs = per <= PE_REG;
+    uint4 rv[PE_REG];
+#pragma unroll
+    for (uint32_t k = 0; k < PE_REG; ++k)
+        rv[k] = (in_regs && w0 + k < w1) ? T.wave_rec[w0 + k] : make_uint4(0u, 0u, 0u, 0u);
     if (w0 < w1) {
         uint32_t r = find_req(T.act_base, nreq, w0 << 6);
         uint32_t next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
         uint4 acc = make_uint4(0u, 0u, 0u, 0u);
-        for (uint32_t w = w0; w < w1; ++w) {
+        auto add = [&](uint32_t w, const uint4 v) {
             while (w >= next) {   // crossing into the next request's waves
                 if (acc.x) atomicAdd(&s_req[0][r], acc.x);
                 if (acc.y) atomicAdd(&s_req[1][r], acc.y);
@@ -1198,15 +1206,20 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
                 ++r;
                 next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
             }
-            const uint4 v = T.wave_rec[w];
             acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+            run += v.x;
+        };
+        if (in_regs) {
+#pragma unroll
+            for (uint32_t k = 0; k < PE_REG; ++k)
+                if (w0 + k < w1) add(w0 + k, rv[k]);
+        } else {
+            for (uint32_t w = w0; w < w1; ++w) add(w, T.wave_rec[w]);
         }
         if (acc.x) atomicAdd(&s_req[0][r], acc.x);
         if (acc.y) atomicAdd(&s_req[1][r], acc.y);
         if (acc.z) atomicAdd(&s_req[2][r], acc.z);
         if (acc.w) atomicAdd(&s_req[3][r], acc.w);
-        run = 0;
-        for (uint32_t w = w0; w < w1; ++w) run += T.wave_rec[w].x;
     }
     // workgroup exclusive scan of the run totals
     const uint32_t l = lane_id(), wv = t >> 6;
@@ -1221,9 +1234,19 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
     uint32_t before = 0;
     for (uint32_t k = 0; k < wv; ++k) before += s_wave[k];
     uint32_t off = before + incl - run;
-    for (uint32_t w = w0; w < w1; ++w) {
-        T.wave_off[w] = off;
-        off += T.wave_rec[w].x;
+    if (in_regs) {
+#pragma unroll
+        for (uint32_t k = 0; k < PE_REG; ++k) {
+            if (w0 + k < w1) {
+                T.wave_off[w0 + k] = off;
+                off += rv[k].x;
+            }
+        }
+    } else {
+        for (uint32_t w = w0; w < w1; ++w) {
+            T.wave_off[w] = off;
+            off += T.wave_rec[w].x;
+        }
     }
     if (t == PE_THREADS - 1) T.wave_off[nw] = off;   // == total survivors
     __syncthreads();
