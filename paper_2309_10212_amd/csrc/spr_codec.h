@@ -84,12 +84,35 @@ __device__ __forceinline__ void inv4(int32_t &p0, int32_t &p1, int32_t &p2, int3
 // entry per plane with refinement bits (first bit | plane << 10 | coefficients
 // listed before it << 16; at most 29 planes plus a spare slot), ev the newly
 // significant coefficients in stream order (at most 64 plus a spare slot).
+// dep4 is the 4-bit deposit table: byte 16*mask + src holds the low
+// popcount(mask) bits of src placed, in ascending order, at the set bits of
+// mask.  It is filled once per workgroup by fill_dep4.
 template <int RWMAX>
 struct DecodeLds {
     uint32_t rec[(RWMAX + 2) * 64];
     uint32_t run[30 * 64];
+    uint32_t dep4[64];
     uint8_t ev[65 * 64];
 };
+
+// Lane l writes table bytes 4l .. 4l+3 (mask l/4, sources 4(l%4) .. +3).
+// The caller synchronises the workgroup before the first decode.
+template <int RWMAX>
+__device__ __forceinline__ void fill_dep4(DecodeLds<RWMAX> &L, uint32_t lane) {
+    const uint32_t mask = lane >> 2;
+    uint32_t word = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < 4; ++c) {
+        const uint32_t src = 4u * (lane & 3u) + c;
+        uint32_t out = 0, r = 0;
+#pragma unroll
+        for (uint32_t b = 0; b < 4; ++b) {
+            if ((mask >> b) & 1u) { out |= ((src >> r) & 1u) << b; ++r; }
+        }
+        word |= out << (8u * c);
+    }
+    L.dep4[lane] = word;
+}
 
 // 64 bits of the record from bit position pos (pos < 32 * RWMAX).
 __device__ __forceinline__ uint64_t rec_window(const uint32_t *rec, uint32_t lane, uint32_t pos) {
@@ -120,19 +143,31 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t x, uint32_t r) {
     return b;
 }
 
-// m[j] |= bit j of D at plane k, for the 64 coefficients.  A half that is
-// zero on every lane of the wave (the high coefficients of early planes)
-// is skipped: OR-ing zeros changes nothing.
+// m[j] |= bit j of D at plane k, for the 64 coefficients.  A group of 16
+// coefficients whose bits are zero on every lane of the wave (the high
+// coefficients of early planes) is skipped: OR-ing zeros changes nothing.
 __device__ __forceinline__ void or_plane(uint32_t (&m)[64], uint64_t D, uint32_t k) {
-    const uint32_t lo = (uint32_t)D, hi = (uint32_t)(D >> 32);
-    if (__ballot(lo != 0u) != 0ull) {
 #pragma unroll
-        for (int j = 0; j < 32; ++j) m[j] |= ((lo >> j) & 1u) << k;
-    }
-    if (__ballot(hi != 0u) != 0ull) {
+    for (int g = 0; g < 4; ++g) {
+        const uint32_t d = (uint32_t)(D >> (16 * g)) & 0xFFFFu;
+        if (__ballot(d != 0u) != 0ull) {
 #pragma unroll
-        for (int j = 0; j < 32; ++j) m[32 + j] |= ((hi >> j) & 1u) << k;
+            for (int j = 0; j < 16; ++j) m[16 * g + j] |= ((d >> j) & 1u) << k;
+        }
     }
+}
+
+// Deposit of the low bits of b at the set bits of mask (ascending), 32 bits
+// wide, four mask bits at a time through the table.
+__device__ __forceinline__ uint32_t deposit32(const uint8_t *dep4, uint32_t mask, uint32_t b) {
+    uint32_t D = 0, r = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t mn = (mask >> (4 * i)) & 15u;
+        D |= (uint32_t)dep4[mn * 16u + ((b >> r) & 15u)] << (4 * i);   // r <= 28 here
+        r += (uint32_t)__builtin_popcount(mn);
+    }
+    return D;
 }
 
 // Decodes the record into q[64] (raster order) and the block exponent.
@@ -155,7 +190,15 @@ __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, 
     uint32_t pos = 9, c = 0, nev = 0, nrun = 0, k_top = 0;
     int k = 29;
     bool scanning = false;   // a scan continues (its group-test bit was read already)
-    bool live = true;
+    // Planes above the first significant coefficient have no refinement bits
+    // and end at their first group test, a 0: skip the run of them at once
+    // (at most all 30 planes; 9 + 30 bits always lie inside the record).
+    {
+        const uint32_t z0 = (uint32_t)__builtin_ctzll(rec_window(L.rec, lane, pos) | (1ull << 30));
+        pos += z0;
+        k -= (int)z0;
+    }
+    bool live = k >= 0;
     while (live) {
         const uint64_t win = rec_window(L.rec, lane, pos);
         const uint64_t cand = c >= 64u ? 0ull : (~S & (~0ull << c));
@@ -210,22 +253,11 @@ __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, 
         const uint64_t bits = rec_window(L.rec, lane, info & 1023u);
         // deposit, in 32-bit halves: the refinement bits of coefficients 32..63
         // follow those of 0..31 (as many as the low half has significant ones)
-        uint32_t Dlo = 0, Dhi = 0;
-        uint32_t todo = (uint32_t)Sr, b32 = (uint32_t)bits;
-        while (todo != 0u) {
-            const uint32_t j = (uint32_t)__builtin_ctz(todo);
-            todo &= todo - 1u;
-            Dlo |= (b32 & 1u) << j;
-            b32 >>= 1;
-        }
-        todo = (uint32_t)(Sr >> 32);
-        b32 = (uint32_t)(bits >> __builtin_popcount((uint32_t)Sr));
-        while (todo != 0u) {
-            const uint32_t j = (uint32_t)__builtin_ctz(todo);
-            todo &= todo - 1u;
-            Dhi |= (b32 & 1u) << j;
-            b32 >>= 1;
-        }
+        const uint8_t *dep4 = reinterpret_cast<const uint8_t *>(L.dep4);
+        const uint32_t slo = (uint32_t)Sr, shi = (uint32_t)(Sr >> 32);
+        const uint32_t Dlo = deposit32(dep4, slo, (uint32_t)bits);
+        uint32_t Dhi = 0;
+        if (__ballot(shi != 0u) != 0ull) Dhi = deposit32(dep4, shi, (uint32_t)(bits >> __builtin_popcount(slo)));
         uint64_t Sn = Sr;
         for (; e < ne; ++e) Sn |= 1ull << L.ev[e * 64 + lane];
         or_plane(m, ((uint64_t)Dhi << 32 | Dlo) | (Sn & ~Sr), (info >> 10) & 31u);

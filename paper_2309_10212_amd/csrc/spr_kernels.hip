@@ -51,6 +51,8 @@ __device__ __forceinline__ void decode_to(const uint32_t *__restrict__ rec, int 
 __global__ __launch_bounds__(64) void k_decode_ids(VolDev V, const uint32_t *ids, uint32_t n, float *out) {
     __shared__ DecodeLds<32> L;
     const uint32_t lane = threadIdx.x;
+    fill_dep4(L, lane);
+    __syncthreads();
     for (uint32_t i = blockIdx.x * 64 + lane; i < n; i += gridDim.x * 64) {
         const uint32_t *rec = V.stream + (size_t)ids[i] * (size_t)V.rec_words;
         decode_to<32>(rec, V.rate, L, lane, out + (size_t)i * 64);
@@ -63,6 +65,8 @@ template <int RWMAX>
 __global__ __launch_bounds__(64) void k_block_ranges(VolDev V, float2 *blk) {
     __shared__ DecodeLds<RWMAX> L;
     const uint32_t lane = threadIdx.x;
+    fill_dep4(L, lane);
+    __syncthreads();
     for (uint64_t b = blockIdx.x * 64ull + lane; b < V.nblocks; b += (uint64_t)gridDim.x * 64) {
         const uint32_t *rec = V.stream + b * (uint64_t)V.rec_words;
         int bx = (int)(b % (uint64_t)V.nb[0]);
@@ -220,46 +224,72 @@ constexpr uint32_t TR_BUF = 16;
 // of its remaining parameter range), up to this many traversal lanes.
 constexpr uint32_t SEG_TARGET = 262144;
 
-__global__ void k_pass_begin(PassCtl *ctl, Table T, int is_init) {
-    if (threadIdx.x < 64) ctl->hist[threadIdx.x] = 0;
-    if (threadIdx.x != 0) return;
-    ctl->pass += 1;
-    ctl->n_vis = 0; ctl->v_adm = 0; ctl->n_actblk = 0; ctl->n_miss = 0; ctl->n_hit = 0;
-    ctl->cursor = 0; ctl->served = 0; ctl->deferred = 0; ctl->need = 0; ctl->evict_T = 64;
-    ctl->evict_done_blocks = 0; ctl->evicted = 0; ctl->terminated = 0; ctl->pairs = 0; ctl->overflow = 0;
+// Inclusive wave scan of v; *total receives the sum over the wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t *total) {
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(v, off);
+        if ((int)l >= off) v += o;
+    }
+    *total = __shfl(v, 63);
+    return v;
+}
+
+// One wave; lane i handles requests i, i + 64, ... so the per-request loads
+// are issued together and the index spaces come from wave scans.
+__global__ __launch_bounds__(64) void k_pass_begin(PassCtl *ctl, Table T, int is_init) {
+    const uint32_t l = lane_id();
+    ctl->hist[l] = 0;
     const uint32_t nreq = T.hdr[0];
-    uint32_t A = 0, P = 0, rays = 0, AT = 0;
+    ReqState *st0 = l < nreq ? T.reqs[l].st : nullptr;
+    const uint32_t na0 = st0 ? st0->n_act : 0u, ns0 = st0 ? st0->n_spec : 0u, ps0 = st0 ? st0->passes : 0u;
     // traversal lanes per ray: a power of two up to 16 while the pass stays
     // within SEG_TARGET lanes over all requests; only for requests whose
     // slots fit one lane's staging buffer (the lanes' lists are merged after
     // the walk)
-    uint32_t all_na = 0;
-    for (uint32_t r = 0; r < nreq; ++r) all_na += T.reqs[r].st->n_act;
+    uint32_t my = na0;
+    for (uint32_t r = l + 64u; r < nreq; r += 64u) my += T.reqs[r].st->n_act;
+    uint32_t all_na;
+    (void)wave_incl_scan(my, &all_na);
     uint32_t segs_all = 1;
     if (!is_init && all_na > 0) {
         const uint32_t want = SEG_TARGET / all_na;
         while (segs_all < 16u && 2u * segs_all <= want) segs_all *= 2u;
     }
-    for (uint32_t r = 0; r < nreq; ++r) {
-        ReqState *st = T.reqs[r].st;
-        uint32_t na = st->n_act, ns = st->n_spec;
+    uint32_t A = 0, P = 0, rays = 0, AT = 0;   // running bases, wave-uniform
+    for (uint32_t r0 = 0; r0 < nreq; r0 += 64u) {
+        const uint32_t r = r0 + l;
+        const bool valid = r < nreq;
+        ReqState *st = r0 == 0 ? st0 : (valid ? T.reqs[r].st : nullptr);
+        const uint32_t na = r0 == 0 ? na0 : (valid ? st->n_act : 0u);
+        const uint32_t ns = r0 == 0 ? ns0 : (valid ? st->n_spec : 0u);
+        const uint32_t ps = r0 == 0 ? ps0 : (valid ? st->passes : 0u);
         const uint32_t segs = (na > 0 && ns <= TR_BUF) ? segs_all : 1u;
-        st->segs = segs;
-        T.trav_base[r] = AT;
-        AT += round64(na * segs);
-        T.act_base[r] = A;
-        T.pair_base[r] = P;
-        st->n_act_prev = na;
-        st->last_nspec = ns;
-        st->last_pairs = 0; st->last_deferred = 0; st->last_terminated = 0;
-        if (na > 0 && !is_init) {
-            if (st->passes == 0) st->entered = na;
-            st->passes += 1;
+        const uint32_t a = round64(na), at = round64(na * segs), pp = is_init ? 0u : na * ns;
+        uint32_t ta, tat, tp, tr;
+        const uint32_t ia = wave_incl_scan(a, &ta), iat = wave_incl_scan(at, &tat), ip = wave_incl_scan(pp, &tp);
+        (void)wave_incl_scan(na, &tr);
+        if (valid) {
+            st->segs = segs;
+            T.trav_base[r] = AT + iat - at;
+            T.act_base[r] = A + ia - a;
+            T.pair_base[r] = P + ip - pp;
+            st->n_act_prev = na;
+            st->last_nspec = ns;
+            st->last_pairs = 0; st->last_deferred = 0; st->last_terminated = 0;
+            if (na > 0 && !is_init) {
+                if (ps == 0) st->entered = na;
+                st->passes = ps + 1u;
+            }
         }
-        A += round64(na);
-        P += is_init ? 0u : na * ns;
-        rays += na;
+        A += ta; P += tp; AT += tat; rays += tr;
     }
+    if (l != 0) return;
+    ctl->pass += 1;
+    ctl->n_vis = 0; ctl->v_adm = 0; ctl->n_actblk = 0; ctl->n_miss = 0; ctl->n_hit = 0;
+    ctl->cursor = 0; ctl->served = 0; ctl->deferred = 0; ctl->need = 0; ctl->evict_T = 64;
+    ctl->evict_done_blocks = 0; ctl->evicted = 0; ctl->terminated = 0; ctl->pairs = 0; ctl->overflow = 0;
     ctl->rays = rays;
     T.act_base[nreq] = A;
     T.pair_base[nreq] = P;
@@ -885,6 +915,8 @@ __global__ __launch_bounds__(256) void k_assign_scatter(PassCtl *ctl, Table T, c
 // Decode the misses into their slots (Sec. 3.5), one thread per block.
 __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols, Work W, Cache C) {
     __shared__ DecodeLds<32> L;
+    fill_dep4(L, threadIdx.x);
+    __syncthreads();
     const uint32_t m = ctl->assigned;
     for (uint32_t i = blockIdx.x * 64 + threadIdx.x; i < m; i += gridDim.x * 64) {
         uint64_t e = W.miss_list[i];
