@@ -59,8 +59,7 @@ def kernel_bytes(name, c, rate):
         "k_init_rays": 28 * NP,                    # ray state, image, hit record, active entry
         "k_traverse": 8 * A + 4 * S + 8 * V,
         "k_dedupe": 4 * S + 12 * P + 12 * V,
-        "k_mark": 20 * V + 16 * K,
-        "k_lookup": 16 * K + 8 * M,
+        "k_mark": 20 * V + 16 * K + 8 * M,
         "k_assign_scatter": 32 * M + 4 * S + 28 * Ps,
         "k_decode": (8 * rate + 268) * M,
         "k_raytrace": 36 * Ps + 532 * V,
@@ -77,7 +76,7 @@ def hbm_fractions(c, rate, steps, ms_per_step, passes, decoded, decode_ms, peak_
     against it, blocks decoded/s against 8 TB/s over a decode's bytes per
     block, peak memory against the 288 GB of HBM."""
     names = ("k_block_ranges", "k_fine_grid", "k_coarse_grid", "k_iso_masks", "k_init_rays", "k_traverse", "k_dedupe",
-             "k_mark", "k_lookup", "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_compact")
+             "k_mark", "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_compact")
     byts = sum(kernel_bytes(k, c, rate) or 0 for k in names) / max(steps, 1)
     t_floor_ms = byts / (HBM_PEAK_GBS * 1e9) * 1e3
     frac_t = t_floor_ms / ms_per_step if ms_per_step > 0 else None
@@ -283,7 +282,7 @@ def main():
     rays = sum(i["rays_entered"] for i in infos)
     passes = sum(i["passes"] for i in infos)
     value = rays / elapsed
-    PASS_KERNELS = ("k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_evict_hist",
+    PASS_KERNELS = ("k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_evict_hist",
                     "k_evict", "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact")
     dev_ms_all = sum(ms for ms, _ in ktimes.values())
     # pass kernels only (the set-up pass also runs k_pass_begin/k_pass_end/k_compact once per step)

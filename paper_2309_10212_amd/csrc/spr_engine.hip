@@ -213,7 +213,6 @@ PassGrids grids_for(const spr_ctx *c, uint64_t max_A, uint64_t max_P) {
     pg.rays = g(max_A, 256, 2048);
     pg.pairs = g(max_P, 256, 2048);
     pg.dedupe = g(max_P, 1024, 2048);
-    pg.blocks = g(8 * max_P, 256, 2048);
     pg.slots = g(c->cache.n_slots, 256, 2048);
     pg.assign = 256;
     pg.scatter = g(max_P, 256, 2048);
@@ -242,13 +241,13 @@ spr_status ensure_work(spr_ctx *c, uint64_t P) {
     Work &W = c->work;
     size_t oP = W.cap_P, oK = W.cap_K;
     dfree(c, W.vis_list, oP); dfree(c, W.vis_off, oP);
-    dfree(c, W.act_list, oK); dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
+    dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
     dfree(c, W.pair_rank, oP); dfree(c, W.s_ray, oP); dfree(c, W.s_q, oP); dfree(c, W.s_vi, oP);
     dfree(c, W.vis_nsl, 8 * oP);
     W.cap_P = 0; W.cap_K = 0;
     uint64_t cP = P, cK = 8 * P;
     CHK(dalloc(c, cP, &W.vis_list)); CHK(dalloc(c, cP, &W.vis_off));
-    CHK(dalloc(c, cK, &W.act_list)); CHK(dalloc(c, cK, &W.miss_list)); CHK(dalloc(c, cK, &W.miss_slot));
+    CHK(dalloc(c, cK, &W.miss_list)); CHK(dalloc(c, cK, &W.miss_slot));
     CHK(dalloc(c, cP, &W.pair_rank)); CHK(dalloc(c, cP, &W.s_ray)); CHK(dalloc(c, cP, &W.s_q));
     CHK(dalloc(c, cP, &W.s_vi)); CHK(dalloc(c, 8 * cP, &W.vis_nsl));
     W.cap_P = (uint32_t)cP;
@@ -322,7 +321,7 @@ spr_status graph_pass(spr_ctx *c, const Table &T, const PassGrids &g, hipGraph_t
 }
 
 // Profiling: add one recorded event set's kernel intervals to their slots.
-constexpr int PASS_SLOTS[PASS_KERNELS] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12};
+constexpr int PASS_SLOTS[PASS_KERNELS] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
 
 spr_status prof_collect(spr_ctx *c, spr_ctx::ProfRec &rec) {
     if (!rec.pending) return SPR_OK;
@@ -443,7 +442,7 @@ spr_status spr_ctx_destroy(spr_ctx *c) {
     Work &W = c->work;
     size_t oP = W.cap_P, oK = W.cap_K;
     dfree(c, W.vis_list, oP); dfree(c, W.vis_off, oP);
-    dfree(c, W.act_list, oK); dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
+    dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
     dfree(c, W.pair_rank, oP); dfree(c, W.s_ray, oP); dfree(c, W.s_q, oP); dfree(c, W.s_vi, oP);
     size_t ns = c->cache.n_slots;
     dfree(c, c->cache.slots, ns * 64);

@@ -145,7 +145,6 @@ struct Table {
 struct Work {
     uint64_t *vis_list;         // (vol << 32) | block
     uint32_t *vis_off;          // start of the block's run in the sorted pairs
-    uint64_t *act_list;         // active blocks (vol << 32) | block
     uint64_t *miss_list;        // misses (vol << 32) | block
     uint32_t *miss_slot;
     uint32_t *pair_rank;        // per pair index: rank within its block

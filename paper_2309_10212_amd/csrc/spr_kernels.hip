@@ -688,9 +688,11 @@ __global__ __launch_bounds__(256) void k_dedupe(PassCtl *ctl, Table T, const Vol
 // Per visible block: read and clear its pair count.  An admitted block
 // (Sec. 3.4 cache-capacity rule) gets its run of sorted pairs (O_BRays of
 // Sec. 3.6) by block-aggregated bump allocation, and marks itself and its
-// +x/+y/+z face, edge and corner neighbours active (Sec. 3.4); first visitors
-// (per-block pass stamp) append to the active list.  Pairs on blocks beyond
-// the admitted prefix are counted as deferred.
+// +x/+y/+z face, edge and corner neighbours active (Sec. 3.4).  The first
+// visitor of a block this pass (per-block pass stamp) also does its cache
+// lookup (Sec. 3.5): a hit refreshes the slot's LRU stamp, a miss is
+// appended to the miss list.  Pairs on blocks beyond the admitted prefix
+// are counted as deferred.
 
 __device__ __forceinline__ uint32_t admitted_blocks(const PassCtl *ctl) {
     uint32_t nv = ctl->n_vis;
@@ -698,17 +700,17 @@ __device__ __forceinline__ uint32_t admitted_blocks(const PassCtl *ctl) {
     return nv < cap ? nv : cap;
 }
 
-__global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, Work W) {
+__global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, Work W, Cache C) {
     __shared__ uint32_t s_tmp[256 / 64 + 1];
-    __shared__ uint32_t s_def;
+    __shared__ uint32_t s_def, s_act;
     const uint32_t nv = ctl->n_vis;
     const uint32_t vadm = admitted_blocks(ctl);
     const uint32_t pass = ctl->pass;
-    if (threadIdx.x == 0) s_def = 0;
-    uint32_t my_def = 0;
+    if (threadIdx.x == 0) { s_def = 0; s_act = 0; }
+    uint32_t my_def = 0, my_act = 0;
     for (uint32_t x0 = blockIdx.x * 256u; x0 < nv; x0 += gridDim.x * 256u) {
         const uint32_t j = x0 + threadIdx.x;
-        uint32_t cnt = 0, newmask = 0, nnew = 0;
+        uint32_t cnt = 0, missmask = 0, nmiss = 0;
         uint64_t e = 0;
         int bx = 0, by = 0, bz = 0;
         if (j < nv) {
@@ -729,8 +731,14 @@ __global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, 
                         uint32_t *stp = &V.act_stamp[nbid];
                         if (__hip_atomic_load(stp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pass &&
                             atomicExch(stp, pass) != pass) {
-                            newmask |= 1u << o;
-                            nnew++;
+                            my_act++;
+                            const uint32_t sl = V.map[nbid];
+                            if (sl == NONE) {
+                                missmask |= 1u << o;
+                                nmiss++;
+                            } else {
+                                C.stamp[sl] = pass;
+                            }
                         }
                     }
                 }
@@ -740,44 +748,24 @@ __global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, 
         }
         const uint32_t off = block_bump<256>(&ctl->cursor, j < vadm ? cnt : 0u, s_tmp);
         if (j < vadm) W.vis_off[j] = off;
-        uint32_t a = block_bump<256>(&ctl->n_actblk, nnew, s_tmp);
-        if (newmask) {
+        uint32_t mi = block_bump<256>(&ctl->n_miss, nmiss, s_tmp);
+        if (missmask) {
             const VolDev &V = vols[(uint32_t)(e >> 32)];
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
-                if ((newmask >> o) & 1u) {
+                if ((missmask >> o) & 1u) {
                     const int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
                     const uint32_t nbid = (uint32_t)(((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2);
-                    W.act_list[a++] = (e & 0xFFFFFFFF00000000ull) | nbid;
+                    W.miss_list[mi++] = (e & 0xFFFFFFFF00000000ull) | nbid;
                 }
             }
         }
     }
     if (my_def) atomicAdd(&s_def, my_def);
+    if (my_act) atomicAdd(&s_act, my_act);
     __syncthreads();
     if (threadIdx.x == 0 && s_def) atomicAdd(&ctl->deferred, s_def);
-}
-
-// ---------------------------------------------------------------- K3 ------
-// Per active block: cache lookup; a hit refreshes the slot's LRU stamp, a miss
-// is appended to the miss list (Sec. 3.5).
-__global__ __launch_bounds__(256) void k_lookup(PassCtl *ctl, const VolDev *vols, Work W, Cache C) {
-    __shared__ uint32_t s_tmp[256 / 64 + 1];
-    const uint32_t K = ctl->n_actblk;
-    const uint32_t pass = ctl->pass;
-    for (uint32_t x0 = blockIdx.x * 256u; x0 < K; x0 += gridDim.x * 256u) {
-        const uint32_t j = x0 + threadIdx.x;
-        bool miss = false;
-        uint64_t e = 0;
-        if (j < K) {
-            e = W.act_list[j];
-            const uint32_t s = vols[(uint32_t)(e >> 32)].map[(uint32_t)e];
-            miss = s == NONE;
-            if (!miss) C.stamp[s] = pass;
-        }
-        const uint32_t idx = block_bump<256>(&ctl->n_miss, miss ? 1u : 0u, s_tmp);
-        if (miss) W.miss_list[idx] = e;
-    }
+    if (threadIdx.x == 0 && s_act) atomicAdd(&ctl->n_actblk, s_act);
 }
 
 // ---------------------------------------------------------------- K4 ------
@@ -1451,11 +1439,11 @@ hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const V
 }
 
 const char *const PASS_KERNEL_NAMES[PASS_KERNELS] = {
-    "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_evict_hist", "k_evict",
+    "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_evict_hist", "k_evict",
     "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact"};
 
 const char *const PROF_NAMES[PROF_SLOTS] = {
-    "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_lookup", "k_evict_hist", "k_evict",
+    "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_evict_hist", "k_evict",
     "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact",
     "k_block_ranges", "k_fine_grid", "k_coarse_grid", "k_iso_masks", "k_init_rays"};
 
@@ -1469,8 +1457,7 @@ hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev
     mark(); hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, ctl, T, 0);
     mark(); hipLaunchKernelGGL(k_traverse, dim3(g.rays), dim3(256), 0, s, ctl, T, vols);
     mark(); hipLaunchKernelGGL(k_dedupe, dim3(g.dedupe), dim3(256), 0, s, ctl, T, vols, W);
-    mark(); hipLaunchKernelGGL(k_mark, dim3(g.pairs), dim3(256), 0, s, ctl, vols, W);
-    mark(); hipLaunchKernelGGL(k_lookup, dim3(g.blocks), dim3(256), 0, s, ctl, vols, W, C);
+    mark(); hipLaunchKernelGGL(k_mark, dim3(g.pairs), dim3(256), 0, s, ctl, vols, W, C);
     mark(); hipLaunchKernelGGL(k_evict_hist, dim3(g.slots), dim3(256), 0, s, ctl, C);
     mark(); hipLaunchKernelGGL(k_evict, dim3(g.slots), dim3(256), 0, s, ctl, vols, C);
     mark(); hipLaunchKernelGGL(k_assign_scatter, dim3(g.assign + g.scatter), dim3(256), 0, s, ctl, T, vols, W, C, g.assign);

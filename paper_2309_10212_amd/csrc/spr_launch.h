@@ -12,7 +12,6 @@ struct PassGrids {
     uint32_t rays;      // 256-thread groups over the active-ray space
     uint32_t pairs;     // 256-thread groups over the pair space
     uint32_t dedupe;    // 256-thread groups over the pair space, DD_ITEMS pairs per thread
-    uint32_t blocks;    // 256-thread groups over visible/active/miss lists
     uint32_t slots;     // 256-thread groups over cache slots (eviction sweeps)
     uint32_t assign;    // 256-thread groups assigning slots to misses
     uint32_t scatter;   // 256-thread groups scattering pairs
@@ -39,14 +38,14 @@ hipError_t launch_release_volume(hipStream_t s, PassCtl *ctl, const Cache &C, ui
 // path, with ev[5] after the last kernel.
 hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words,
                             hipEvent_t *ev = nullptr);
-constexpr int PASS_KERNELS = 13;
+constexpr int PASS_KERNELS = 12;
 extern const char *const PASS_KERNEL_NAMES[PASS_KERNELS];
 // Profiling slots: the pass kernels, then the load-path and set-up kernels
 // that run outside a pass.
 constexpr int PROF_SLOTS = PASS_KERNELS + 5;
 extern const char *const PROF_NAMES[PROF_SLOTS];
-constexpr int LOAD_SLOTS[3] = {13, 14, 15};           // block ranges, fine grid, coarse grid
-constexpr int INIT_SLOTS[5] = {16, 0, 17, 11, 12};    // masks, pass begin, initial rays, pass end, compact
+constexpr int LOAD_SLOTS[3] = {12, 13, 14};           // block ranges, fine grid, coarse grid
+constexpr int INIT_SLOTS[5] = {15, 0, 16, 10, 11};    // masks, pass begin, initial rays, pass end, compact
 // ev == nullptr: plain launches; else ev[i] is recorded before kernel i and
 // ev[PASS_KERNELS] after the last one.
 hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, const Work &W,
