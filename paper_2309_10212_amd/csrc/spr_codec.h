@@ -80,18 +80,22 @@ __device__ __forceinline__ void inv4(int32_t &p0, int32_t &p1, int32_t &p2, int3
 // what a decoder that stops at the end produces.
 
 // Per-wave LDS of the thread decoder, lane-interleaved ([slot * 64 + lane]):
-// rec holds record words 0 .. RWMAX+1 (2*rate real ones, then zeros), run one
-// entry per plane with refinement bits (first bit | plane << 10 | coefficients
-// listed before it << 16; at most 29 planes plus a spare slot), ev the newly
-// significant coefficients in stream order (at most 64 plus a spare slot).
+// rec holds record words 0 .. RWMAX+1 (2*rate real ones, then zeros); per
+// plane with refinement bits (at most 29 plus a spare slot) run holds the
+// position of its first refinement bit (bits 0..9: it lies inside the record,
+// at most 1024 bits) and, in bits 10..15, the number of coefficients listed
+// before it modulo 64 (1 .. 64 there, so 0 stands for 64); ev lists the newly
+// significant coefficients in stream order (at most 64 plus a spare slot).  The planes
+// with refinement bits are consecutive: entry r is plane k_top - 1 - r, k_top
+// the first significant plane.
 // dep4 is the 4-bit deposit table: byte 16*mask + src holds the low
 // popcount(mask) bits of src placed, in ascending order, at the set bits of
 // mask.  It is filled once per workgroup by fill_dep4.
 template <int RWMAX>
 struct DecodeLds {
     uint32_t rec[(RWMAX + 2) * 64];
-    uint32_t run[30 * 64];
     uint32_t dep4[64];
+    uint16_t run[30 * 64];
     uint8_t ev[65 * 64];
 };
 
@@ -121,6 +125,12 @@ __device__ __forceinline__ uint64_t rec_window(const uint32_t *rec, uint32_t lan
     const uint32_t lo = (uint32_t)(((a1 << 32) | a0) >> s);
     const uint32_t hi = (uint32_t)(((a2 << 32) | a1) >> s);
     return ((uint64_t)hi << 32) | lo;
+}
+
+// Coefficients listed before a recorded plane, from its run entry.
+__device__ __forceinline__ uint32_t run_count(uint16_t v) {
+    const uint32_t n = (uint32_t)v >> 10;
+    return n != 0u ? n : 64u;
 }
 
 // Index of the r-th set bit (from 0, ascending) of x; any value in 0..63 when
@@ -226,7 +236,7 @@ __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, 
         const bool pe = !hit;
         const int kn = pe ? k - 1 : k;
         const bool next_plane = pe && kn >= 0;
-        L.run[nrun * 64 + lane] = npos | ((uint32_t)kn << 10) | (nev << 16);
+        L.run[nrun * 64 + lane] = (uint16_t)((npos & 1023u) | (nev << 10));   // read back only when recorded
         nrun += (next_plane && S != 0ull && npos < B) ? 1u : 0u;
         npos += next_plane ? (uint32_t)__builtin_popcountll(S) : 0u;
         c = pe ? 0u : c;
@@ -243,14 +253,13 @@ __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, 
     uint32_t e = 0;
     {
         // the first significant plane has no refinement bits
-        const uint32_t ne = nrun > 0u ? (L.run[lane] >> 16) : nev;
+        const uint32_t ne = nrun > 0u ? run_count(L.run[lane]) : nev;
         for (; e < ne; ++e) Sr |= 1ull << L.ev[e * 64 + lane];
         or_plane(m, Sr, k_top);
     }
     for (uint32_t r = 0; r < nrun; ++r) {
-        const uint32_t info = L.run[r * 64 + lane];
-        const uint32_t ne = r + 1u < nrun ? (L.run[(r + 1u) * 64 + lane] >> 16) : nev;
-        const uint64_t bits = rec_window(L.rec, lane, info & 1023u);
+        const uint32_t ne = r + 1u < nrun ? run_count(L.run[(r + 1u) * 64 + lane]) : nev;
+        const uint64_t bits = rec_window(L.rec, lane, (uint32_t)L.run[r * 64 + lane] & 1023u);
         // deposit, in 32-bit halves: the refinement bits of coefficients 32..63
         // follow those of 0..31 (as many as the low half has significant ones)
         const uint8_t *dep4 = reinterpret_cast<const uint8_t *>(L.dep4);
@@ -260,7 +269,7 @@ __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, 
         if (__ballot(shi != 0u) != 0ull) Dhi = deposit32(dep4, shi, (uint32_t)(bits >> __builtin_popcount(slo)));
         uint64_t Sn = Sr;
         for (; e < ne; ++e) Sn |= 1ull << L.ev[e * 64 + lane];
-        or_plane(m, ((uint64_t)Dhi << 32 | Dlo) | (Sn & ~Sr), (info >> 10) & 31u);
+        or_plane(m, ((uint64_t)Dhi << 32 | Dlo) | (Sn & ~Sr), k_top - 1u - r);
         Sr = Sn;
     }
 

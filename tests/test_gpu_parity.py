@@ -69,6 +69,45 @@ def test_decode_bitexact(ctx, dims, rate, kind):
     vol.free()
 
 
+def _arbitrary_records(rate, rng):
+    """Records that no encoder writes but the decoder must take as they come:
+    random bits at several densities, and all ones / all zeros / periodic
+    bits with the exponent field varied.  They reach the decoder's edge
+    paths: every plane empty, all 64 coefficients significant before a plane
+    with refinement bits, scans that run out of candidates or of record."""
+    nbits = 64 * rate
+    recs = []
+    for p1 in (0.005, 0.05, 0.3, 0.8, 0.995):
+        bits = (rng.random((128, nbits)) < p1).astype(np.uint8)
+        recs.append(bits)
+    for pat in ("ones", "zeros", "p3", "p7", "p61"):
+        b = np.zeros((64, nbits), np.uint8)
+        for i in range(64):
+            if pat == "ones":
+                b[i, :] = 1
+            elif pat != "zeros":
+                per = int(pat[1:])
+                b[i, (np.arange(nbits) + i) % per == 0] = 1
+            b[i, 1:9] = (np.arange(8) < (i % 9)).astype(np.uint8)
+        recs.append(b)
+    bits = np.concatenate(recs)
+    bits[:, 0] = 1   # every record nonzero
+    return np.packbits(bits, axis=1, bitorder="little").reshape(-1)
+
+
+@pytest.mark.parametrize("rate", list(range(1, 17)))
+def test_decode_bitexact_arbitrary_records(ctx, rate):
+    s = _arbitrary_records(rate, np.random.default_rng(100 + rate))
+    nb = s.size // (8 * rate)
+    dims = (4 * nb, 4, 4)
+    vol = ctx.load_volume(s, dims, rate)
+    ids = np.arange(nb, dtype=np.uint32)
+    got = vol.decode_blocks(ids)
+    ref = oracle.decode_blocks(s, dims, rate, ids)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    vol.free()
+
+
 @pytest.mark.parametrize("dims,rate", [((64, 64, 64), 8), ((37, 29, 23), 2), ((17, 21, 65), 4)])
 def test_grids_bitexact(ctx, dims, rate):
     nx, ny, nz = dims
