@@ -59,9 +59,9 @@ def kernel_bytes(name, c, rate):
         "k_init_rays": 28 * NP,                    # ray state, image, hit record, active entry
         "k_traverse": 8 * A + 4 * S + 8 * V,
         "k_dedupe": 4 * S + 12 * P + 12 * V,
-        "k_mark": 20 * V + 16 * K + 8 * M,
+        "k_mark": 52 * V + 12 * K + 8 * M,      # + the 8 neighbour stamps each visible block tests
         "k_assign_scatter": 32 * M + 4 * S + 28 * Ps,
-        "k_decode": (8 * rate + 268) * M,
+        "k_decode": (8 * rate + 268) * M + 64 * V,   # + each visible block's 8 neighbour slots, read and listed
         "k_raytrace": 36 * Ps + 532 * V,
         "k_composite": 8 * A + 4 * S + 20 * P,
         "k_compact": 12 * A,
