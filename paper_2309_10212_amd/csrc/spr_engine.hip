@@ -550,10 +550,11 @@ static void free_volume_buffers(spr_ctx *c, VolDev &V, size_t stream_bytes) {
     V.stream = nullptr;
     dfree(c, V.fine, nb);
     dfree(c, V.coarse, nc);
-    dfree(c, V.map, nb);
-    dfree(c, V.blk_cnt, nb);
-    dfree(c, V.vis_idx, nb);
-    dfree(c, V.act_stamp, nb);
+    const uint64_t ns = bidx_count(V);
+    dfree(c, V.map, ns);
+    dfree(c, V.blk_cnt, ns);
+    dfree(c, V.vis_idx, ns);
+    dfree(c, V.act_stamp, ns);
     dfree(c, V.blk, nb);
 }
 
@@ -585,6 +586,7 @@ spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, co
         V.tb[a] = (V.n[a] - 1 + 3) / 4;
         V.tc[a] = (V.tb[a] + 3) / 4;
     }
+    if (bidx_count(V) >= 0xFFFFFFF0ull) return fail(SPR_E_INVALID, "too many blocks");
     V.rate = (int)d->rate_bits;
     V.rec_words = 2 * (int)d->rate_bits;
     V.nblocks = nb;
@@ -597,10 +599,10 @@ spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, co
         V.stream = (const uint32_t *)sp;
         if ((st = dalloc(c, nb, &V.fine)) != SPR_OK) break;
         if ((st = dalloc(c, nc, &V.coarse)) != SPR_OK) break;
-        if ((st = dalloc(c, nb, &V.map)) != SPR_OK) break;
-        if ((st = dalloc(c, nb, &V.blk_cnt)) != SPR_OK) break;
-        if ((st = dalloc(c, nb, &V.vis_idx)) != SPR_OK) break;
-        if ((st = dalloc(c, nb, &V.act_stamp)) != SPR_OK) break;
+        if ((st = dalloc(c, bidx_count(V), &V.map)) != SPR_OK) break;
+        if ((st = dalloc(c, bidx_count(V), &V.blk_cnt)) != SPR_OK) break;
+        if ((st = dalloc(c, bidx_count(V), &V.vis_idx)) != SPR_OK) break;
+        if ((st = dalloc(c, bidx_count(V), &V.act_stamp)) != SPR_OK) break;
         if ((st = dalloc(c, nb, &V.blk)) != SPR_OK) break;
     } while (0);
     if (st != SPR_OK) {
@@ -608,10 +610,10 @@ spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, co
         return st;
     }
     hipError_t e = hipMemcpyAsync(sp, host_stream, bytes, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.map, nb, NONE);
-    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.blk_cnt, nb, 0);
-    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.vis_idx, nb, 0);
-    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.act_stamp, nb, 0);
+    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.map, bidx_count(V), NONE);
+    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.blk_cnt, bidx_count(V), 0);
+    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.vis_idx, bidx_count(V), 0);
+    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.act_stamp, bidx_count(V), 0);
     if (e == hipSuccess) e = launch_load_grids(c->stream, V);
     c->h_vols[idx] = V;
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_vols + idx, &c->h_vols[idx], sizeof(VolDev), hipMemcpyHostToDevice, c->stream);

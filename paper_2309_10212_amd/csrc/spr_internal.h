@@ -45,6 +45,27 @@ struct VolDev {
     uint32_t pad;
 };
 
+// Index of block (bx, by, bz) in the per-block state arrays (map, blk_cnt,
+// vis_idx, act_stamp): the 64 blocks of a coarse cell are contiguous, at
+// (bx&3) + 4(by&3) + 16(bz&3) (the order of the isovalue mask bits), and the
+// coarse cells follow in raster order, so a block's +x/+y/+z neighbourhood
+// mostly lies in the same 256 bytes.  Block ids everywhere else are linear,
+// (bz*nb[1] + by)*nb[0] + bx.
+__device__ __forceinline__ uint32_t bidx_xyz(const VolDev &V, int bx, int by, int bz) {
+    const uint32_t cell = ((uint32_t)(bz >> 2) * (uint32_t)V.nc[1] + (uint32_t)(by >> 2)) * (uint32_t)V.nc[0] +
+                          (uint32_t)(bx >> 2);
+    return cell * 64u + (uint32_t)((bx & 3) | ((by & 3) << 2) | ((bz & 3) << 4));
+}
+
+__device__ __forceinline__ uint32_t bidx(const VolDev &V, uint32_t b) {
+    const uint32_t nb0 = (uint32_t)V.nb[0], nb1 = (uint32_t)V.nb[1];
+    const uint32_t r = b / nb0;
+    return bidx_xyz(V, (int)(b - r * nb0), (int)(r % nb1), (int)(r / nb1));
+}
+
+// Entries of each per-block state array (whole coarse cells).
+inline uint64_t bidx_count(const VolDev &V) { return (uint64_t)V.nc[0] * V.nc[1] * V.nc[2] * 64u; }
+
 // Per-pair raytrace result (the RGBZ buffer of Sec. 4.3): t = +inf for no hit.
 struct Rgbz {
     double t;

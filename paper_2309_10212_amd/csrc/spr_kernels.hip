@@ -645,25 +645,28 @@ __global__ __launch_bounds__(256) void k_dedupe(PassCtl *ctl, Table T, const Vol
     const uint32_t vol0 = T.reqs[r0].vol;
     constexpr uint32_t SPAN = 256u * DD_ITEMS;
     for (uint32_t x0 = blockIdx.x * SPAN; x0 < P; x0 += gridDim.x * SPAN) {
-        uint32_t b[DD_ITEMS], vol[DD_ITEMS];
+        uint32_t b[DD_ITEMS], vol[DD_ITEMS], bi[DD_ITEMS];
         uint32_t firsts = 0, nf = 0;
 #pragma unroll
         for (int k = 0; k < DD_ITEMS; ++k) {
             const uint32_t x = x0 + (uint32_t)k * 256u + threadIdx.x;
             b[k] = NONE;
             vol[k] = 0;
+            bi[k] = 0;
             if (x < P) {
                 const uint32_t r = find_req(T.pair_base, nreq, x);
                 const ReqDev &q = T.reqs[r];
                 b[k] = q.pair_blk[x - T.pair_base[r]];
                 vol[k] = q.vol;
                 if (b[k] != NONE) {
-                    const uint32_t rank = atomicAdd(&vols[vol[k]].blk_cnt[b[k]], 1u);
+                    const VolDev &V = vols[vol[k]];
+                    bi[k] = bidx(V, b[k]);
+                    const uint32_t rank = atomicAdd(&V.blk_cnt[bi[k]], 1u);
                     W.pair_rank[x] = rank;
                     if (rank == 0) {
                         if (b[k] == b0 && vol[k] == vol0) {
                             W.vis_list[0] = ((uint64_t)vol0 << 32) | b0;
-                            vols[vol0].vis_idx[b0] = 0u;
+                            V.vis_idx[bi[k]] = 0u;
                         } else {
                             firsts |= 1u << k;
                             nf++;
@@ -677,7 +680,7 @@ __global__ __launch_bounds__(256) void k_dedupe(PassCtl *ctl, Table T, const Vol
         for (int k = 0; k < DD_ITEMS; ++k) {
             if ((firsts >> k) & 1u) {
                 W.vis_list[idx] = ((uint64_t)vol[k] << 32) | b[k];
-                vols[vol[k]].vis_idx[b[k]] = idx;
+                vols[vol[k]].vis_idx[bi[k]] = idx;
                 idx++;
             }
         }
@@ -717,22 +720,23 @@ __global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, 
             e = W.vis_list[j];
             const VolDev &V = vols[(uint32_t)(e >> 32)];
             const uint32_t b = (uint32_t)e;
-            cnt = V.blk_cnt[b];
-            V.blk_cnt[b] = 0u;
+            bx = (int)(b % (uint32_t)V.nb[0]);
+            by = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
+            bz = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
+            const uint32_t bi = bidx_xyz(V, bx, by, bz);
+            cnt = V.blk_cnt[bi];
+            V.blk_cnt[bi] = 0u;
             if (j < vadm) {
-                bx = (int)(b % (uint32_t)V.nb[0]);
-                by = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
-                bz = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
 #pragma unroll
                 for (int o = 0; o < 8; ++o) {
                     const int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
                     if (x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2]) {
-                        const uint32_t nbid = (uint32_t)(((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2);
-                        uint32_t *stp = &V.act_stamp[nbid];
+                        const uint32_t nbi = bidx_xyz(V, x2, y2, z2);
+                        uint32_t *stp = &V.act_stamp[nbi];
                         if (__hip_atomic_load(stp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pass &&
                             atomicExch(stp, pass) != pass) {
                             my_act++;
-                            const uint32_t sl = V.map[nbid];
+                            const uint32_t sl = V.map[nbi];
                             if (sl == NONE) {
                                 missmask |= 1u << o;
                                 nmiss++;
@@ -836,7 +840,8 @@ __global__ __launch_bounds__(256) void k_evict(PassCtl *ctl, const VolDev *vols,
                 uint32_t age = pass - st;
                 if (st != pass && (age > 63u ? 63u : age) >= T) {
                     ev = true;
-                    vols[(uint32_t)(o >> 32)].map[(uint32_t)o] = NONE;
+                    const VolDev &V = vols[(uint32_t)(o >> 32)];
+                    V.map[bidx(V, (uint32_t)o)] = NONE;
                     C.owner[s] = ~0ull;
                 }
             }
@@ -871,7 +876,8 @@ __global__ __launch_bounds__(256) void k_assign_scatter(PassCtl *ctl, Table T, c
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += assign_groups * blockDim.x) {
             uint64_t e = W.miss_list[i];
             uint32_t sl = C.free_stack[base + i];
-            vols[(uint32_t)(e >> 32)].map[(uint32_t)e] = sl;
+            const VolDev &V = vols[(uint32_t)(e >> 32)];
+            V.map[bidx(V, (uint32_t)e)] = sl;
             C.owner[sl] = e;
             C.stamp[sl] = pass;
             W.miss_slot[i] = sl;
@@ -887,7 +893,8 @@ __global__ __launch_bounds__(256) void k_assign_scatter(PassCtl *ctl, Table T, c
         uint32_t qq = x - T.pair_base[r];
         uint32_t b = q.pair_blk[qq];
         if (b == NONE) continue;
-        uint32_t vi = vols[q.vol].vis_idx[b];
+        const VolDev &V = vols[q.vol];
+        uint32_t vi = V.vis_idx[bidx(V, b)];
         if (vi >= vadm) continue;
         uint32_t dst = W.vis_off[vi] + W.pair_rank[x];
         const ReqState *st = q.st;
@@ -931,7 +938,7 @@ __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols,
         for (int o = 0; o < 8; ++o) {
             const int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
             const bool ok = x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2];
-            nsl[o] = ok ? V.map[((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2] : NONE;
+            nsl[o] = ok ? V.map[bidx_xyz(V, x2, y2, z2)] : NONE;
         }
         uint4 *dst = reinterpret_cast<uint4 *>(W.vis_nsl + (size_t)v * 8);
         dst[0] = make_uint4(nsl[0], nsl[1], nsl[2], nsl[3]);
@@ -1139,7 +1146,7 @@ __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const 
                     break;
                 }
                 my_pairs++;
-                const bool served = all_served || V.vis_idx[b] < vadm;
+                const bool served = all_served || V.vis_idx[bidx(V, b)] < vadm;
                 if (stopped || term) {
                     if (!served) my_def++;
                     continue;
