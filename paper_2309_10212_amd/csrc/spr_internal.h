@@ -63,6 +63,35 @@ __device__ __forceinline__ uint32_t bidx(const VolDev &V, uint32_t b) {
     return bidx_xyz(V, (int)(b - r * nb0), (int)(r % nb1), (int)(r / nb1));
 }
 
+// The fields of a volume that the per-block bookkeeping kernels use, read
+// once into registers.  Read through a reference into device memory, they
+// are reloaded after every store or atomic (the compiler cannot rule out that
+// the store changed them), which puts several dependent round trips to memory
+// in front of every access.
+struct VolState {
+    uint32_t *map, *blk_cnt, *vis_idx, *act_stamp;
+    int nb0, nb1, nb2, nc0, nc1;
+};
+
+__device__ __forceinline__ VolState vol_state(const VolDev &V) {
+    VolState s;
+    s.map = V.map; s.blk_cnt = V.blk_cnt; s.vis_idx = V.vis_idx; s.act_stamp = V.act_stamp;
+    s.nb0 = V.nb[0]; s.nb1 = V.nb[1]; s.nb2 = V.nb[2]; s.nc0 = V.nc[0]; s.nc1 = V.nc[1];
+    return s;
+}
+
+__device__ __forceinline__ uint32_t bidx_xyz(const VolState &S, int bx, int by, int bz) {
+    const uint32_t cell = ((uint32_t)(bz >> 2) * (uint32_t)S.nc1 + (uint32_t)(by >> 2)) * (uint32_t)S.nc0 +
+                          (uint32_t)(bx >> 2);
+    return cell * 64u + (uint32_t)((bx & 3) | ((by & 3) << 2) | ((bz & 3) << 4));
+}
+
+__device__ __forceinline__ uint32_t bidx(const VolState &S, uint32_t b) {
+    const uint32_t nb0 = (uint32_t)S.nb0, nb1 = (uint32_t)S.nb1;
+    const uint32_t r = b / nb0;
+    return bidx_xyz(S, (int)(b - r * nb0), (int)(r % nb1), (int)(r / nb1));
+}
+
 // Entries of each per-block state array (whole coarse cells).
 inline uint64_t bidx_count(const VolDev &V) { return (uint64_t)V.nc[0] * V.nc[1] * V.nc[2] * 64u; }
 

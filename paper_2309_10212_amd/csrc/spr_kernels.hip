@@ -716,33 +716,51 @@ __global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, 
         uint32_t cnt = 0, missmask = 0, nmiss = 0;
         uint64_t e = 0;
         int bx = 0, by = 0, bz = 0;
+        VolState S{};
         if (j < nv) {
             e = W.vis_list[j];
-            const VolDev &V = vols[(uint32_t)(e >> 32)];
+            S = vol_state(vols[(uint32_t)(e >> 32)]);
             const uint32_t b = (uint32_t)e;
-            bx = (int)(b % (uint32_t)V.nb[0]);
-            by = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
-            bz = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
-            const uint32_t bi = bidx_xyz(V, bx, by, bz);
-            cnt = V.blk_cnt[bi];
-            V.blk_cnt[bi] = 0u;
+            const uint32_t rr = b / (uint32_t)S.nb0;
+            bx = (int)(b - rr * (uint32_t)S.nb0);
+            by = (int)(rr % (uint32_t)S.nb1);
+            bz = (int)(rr / (uint32_t)S.nb1);
+            const uint32_t bi = bidx_xyz(S, bx, by, bz);
+            const gptr<uint32_t> bc = as_global(S.blk_cnt);
+            cnt = bc[bi];
+            bc[bi] = 0u;
             if (j < vadm) {
+                // The 8 neighbours in two straight-line steps - claims
+                // (exchange of the pass stamp), then slot map reads - so that
+                // each step's accesses go out together: one round trip per
+                // step, not per neighbour.  A neighbour outside the volume
+                // takes the block's own index (exchanged just before by
+                // neighbour 0, so it returns this pass) and is masked out.
+                const gptr<uint32_t> stamp = as_global(S.act_stamp);
+                const gptr<const uint32_t> map = as_global((const uint32_t *)S.map);
+                uint32_t nbi[8], ex[8], sl[8];
+                uint32_t inside = 0;
 #pragma unroll
                 for (int o = 0; o < 8; ++o) {
                     const int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
-                    if (x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2]) {
-                        const uint32_t nbi = bidx_xyz(V, x2, y2, z2);
-                        uint32_t *stp = &V.act_stamp[nbi];
-                        if (__hip_atomic_load(stp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pass &&
-                            atomicExch(stp, pass) != pass) {
-                            my_act++;
-                            const uint32_t sl = V.map[nbi];
-                            if (sl == NONE) {
-                                missmask |= 1u << o;
-                                nmiss++;
-                            } else {
-                                C.stamp[sl] = pass;
-                            }
+                    const bool ok = x2 < S.nb0 && y2 < S.nb1 && z2 < S.nb2;
+                    nbi[o] = ok ? bidx_xyz(S, x2, y2, z2) : bi;
+                    inside |= ok ? 1u << o : 0u;
+                }
+#pragma unroll
+                for (int o = 0; o < 8; ++o)
+                    ex[o] = __hip_atomic_exchange(stamp + nbi[o], pass, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int o = 0; o < 8; ++o) sl[o] = map[nbi[o]];
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    if (((inside >> o) & 1u) && ex[o] != pass) {   // first visitor this pass: cache lookup
+                        my_act++;
+                        if (sl[o] == NONE) {
+                            missmask |= 1u << o;
+                            nmiss++;
+                        } else {
+                            C.stamp[sl[o]] = pass;
                         }
                     }
                 }
@@ -754,12 +772,11 @@ __global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, 
         if (j < vadm) W.vis_off[j] = off;
         uint32_t mi = block_bump<256>(&ctl->n_miss, nmiss, s_tmp);
         if (missmask) {
-            const VolDev &V = vols[(uint32_t)(e >> 32)];
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
                 if ((missmask >> o) & 1u) {
                     const int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
-                    const uint32_t nbid = (uint32_t)(((uint64_t)z2 * V.nb[1] + y2) * V.nb[0] + x2);
+                    const uint32_t nbid = (uint32_t)(((uint64_t)z2 * (uint32_t)S.nb1 + y2) * (uint32_t)S.nb0 + x2);
                     W.miss_list[mi++] = (e & 0xFFFFFFFF00000000ull) | nbid;
                 }
             }
@@ -928,18 +945,26 @@ __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols,
     const uint32_t wr = gridDim.x - 1u - blockIdx.x;
     for (uint32_t v = wr * 64 + threadIdx.x; v < vadm; v += gridDim.x * 64) {
         const uint64_t e = W.vis_list[v];
-        const VolDev &V = vols[(uint32_t)(e >> 32)];
+        const VolState V = vol_state(vols[(uint32_t)(e >> 32)]);
         const uint32_t b = (uint32_t)e;
-        const int bx = (int)(b % (uint32_t)V.nb[0]);
-        const int by = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
-        const int bz = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
+        const uint32_t rr = b / (uint32_t)V.nb0;
+        const int bx = (int)(b - rr * (uint32_t)V.nb0), by = (int)(rr % (uint32_t)V.nb1), bz = (int)(rr / (uint32_t)V.nb1);
+        // eight independent reads (a neighbour outside the volume reads the
+        // block's own entry and is masked), issued together
+        const gptr<const uint32_t> map = as_global((const uint32_t *)V.map);
         uint32_t nsl[8];
+        uint32_t inside = 0, nbi[8];
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             const int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
-            const bool ok = x2 < V.nb[0] && y2 < V.nb[1] && z2 < V.nb[2];
-            nsl[o] = ok ? V.map[bidx_xyz(V, x2, y2, z2)] : NONE;
+            const bool ok = x2 < V.nb0 && y2 < V.nb1 && z2 < V.nb2;
+            nbi[o] = bidx_xyz(V, ok ? x2 : bx, ok ? y2 : by, ok ? z2 : bz);
+            inside |= ok ? 1u << o : 0u;
         }
+#pragma unroll
+        for (int o = 0; o < 8; ++o) nsl[o] = map[nbi[o]];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) nsl[o] = ((inside >> o) & 1u) ? nsl[o] : NONE;
         uint4 *dst = reinterpret_cast<uint4 *>(W.vis_nsl + (size_t)v * 8);
         dst[0] = make_uint4(nsl[0], nsl[1], nsl[2], nsl[3]);
         dst[1] = make_uint4(nsl[4], nsl[5], nsl[6], nsl[7]);
@@ -1132,9 +1157,13 @@ __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const 
         bool alive = false;
         uint32_t my_pairs = 0, my_def = 0, my_term = 0;
         if (i < st->n_act_prev) {
+            // the request's and volume's fields in registers: through the
+            // references they would be read again after every store
+            uint32_t *const image = q.image, *const ray_state = q.ray_state;
+            spr_hit *const hits = q.hits;
+            const VolState V = vol_state(vols[q.vol]);
             const uint32_t ns = st->last_nspec;
             const uint32_t pix = q.act[st->cur][i];
-            const VolDev &V = vols[q.vol];
             const uint32_t *slots = q.pair_blk + (size_t)i * ns;
             const Rgbz *res = q.rgbz + (size_t)i * ns;
             uint32_t last = NONE;
@@ -1158,19 +1187,19 @@ __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const 
                 }
                 Rgbz rec = res[k];
                 if (rec.t < __builtin_inf()) {
-                    q.image[pix] = rec.rgba;
+                    image[pix] = rec.rgba;
                     spr_hit h;
                     h.t = rec.t;
                     h.block_id = b;
                     h.cell = rec.cell;
-                    q.hits[pix] = h;
+                    hits[pix] = h;
                     term = true;
                     continue;
                 }
                 last = b;
             }
-            if (term) q.ray_state[pix] = RAY_DONE;
-            else if (last != NONE) q.ray_state[pix] = last;
+            if (term) ray_state[pix] = RAY_DONE;
+            else if (last != NONE) ray_state[pix] = last;
             alive = !term;
             my_term = term ? 1u : 0u;
         }
