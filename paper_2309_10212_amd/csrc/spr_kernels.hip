@@ -658,20 +658,49 @@ __global__ __launch_bounds__(256) void k_dedupe(PassCtl *ctl, Table T, const Vol
                 const ReqDev &q = T.reqs[r];
                 b[k] = q.pair_blk[x - T.pair_base[r]];
                 vol[k] = q.vol;
-                if (b[k] != NONE) {
-                    const VolDev &V = vols[vol[k]];
-                    bi[k] = bidx(V, b[k]);
-                    const uint32_t rank = atomicAdd(&V.blk_cnt[bi[k]], 1u);
-                    W.pair_rank[x] = rank;
-                    if (rank == 0) {
-                        if (b[k] == b0 && vol[k] == vol0) {
-                            W.vis_list[0] = ((uint64_t)vol0 << 32) | b0;
-                            V.vis_idx[bi[k]] = 0u;
-                        } else {
-                            firsts |= 1u << k;
-                            nf++;
-                        }
-                    }
+            }
+        }
+        // Ranks.  Adjacent rays share blocks, so a wave's lanes often name
+        // the same block: the lanes of one block form a group, its first lane
+        // adds the group's size to the block's counter, and the members take
+        // consecutive ranks from the returned base.  One atomic per distinct
+        // block of the wave instead of one per pair; the ranks of a block are
+        // still exactly 0 .. count-1.
+        const uint32_t lane = lane_id();
+#pragma unroll
+        for (int k = 0; k < DD_ITEMS; ++k) {
+            const bool valid = b[k] != NONE;
+            if (valid) bi[k] = bidx(vol_state(vols[vol[k]]), b[k]);
+            const uint64_t key = ((uint64_t)vol[k] << 32) | b[k];
+            uint64_t todo = __ballot(valid);
+            uint32_t leader = 0, within = 0, gsize = 0;
+            while (todo != 0ull) {   // once per distinct block of the wave
+                const uint32_t l = (uint32_t)__builtin_ctzll(todo);
+                const uint64_t lk = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(key >> 32), (int)l) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, (int)l);
+                const uint64_t m = __ballot(valid && key == lk);
+                if ((m >> lane) & 1ull) {
+                    leader = l;
+                    within = (uint32_t)__popcll(m & lanemask_lt());
+                }
+                if (lane == l) gsize = (uint32_t)__popcll(m);
+                todo &= ~m;
+            }
+            uint32_t base = 0;
+            if (valid && lane == leader)
+                base = __hip_atomic_fetch_add(as_global(vols[vol[k]].blk_cnt) + bi[k], gsize, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+            base = (uint32_t)__shfl((int)base, (int)leader);
+            if (!valid) continue;
+            const uint32_t rank = base + within;
+            W.pair_rank[x0 + (uint32_t)k * 256u + threadIdx.x] = rank;
+            if (rank == 0) {
+                if (b[k] == b0 && vol[k] == vol0) {
+                    W.vis_list[0] = ((uint64_t)vol0 << 32) | b0;
+                    vols[vol0].vis_idx[bi[k]] = 0u;
+                } else {
+                    firsts |= 1u << k;
+                    nf++;
                 }
             }
         }
