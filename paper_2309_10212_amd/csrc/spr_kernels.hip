@@ -933,19 +933,25 @@ __global__ __launch_bounds__(256) void k_assign_scatter(PassCtl *ctl, Table T, c
     const uint32_t P = ctl->P;
     const uint32_t vadm = admitted_blocks(ctl);
     const uint32_t nthreads = (gridDim.x - assign_groups) * blockDim.x;
+    const uint32_t nreq = ctl->nreq;
     for (uint32_t x = (blockIdx.x - assign_groups) * blockDim.x + threadIdx.x; x < P; x += nthreads) {
-        uint32_t r = find_req(T.pair_base, ctl->nreq, x);
+        // loads in dependency order, all before the stores (through the
+        // references they would be read again after each store)
+        const uint32_t r = find_req(T.pair_base, nreq, x);
         const ReqDev &q = T.reqs[r];
-        uint32_t qq = x - T.pair_base[r];
-        uint32_t b = q.pair_blk[qq];
+        const uint32_t qq = x - T.pair_base[r];
+        const uint32_t *const pblk = q.pair_blk;
+        const ReqState *const st = q.st;
+        const uint32_t *const act = q.act[0], *const act1 = q.act[1];
+        const uint32_t rank = W.pair_rank[x];
+        const VolState V = vol_state(vols[q.vol]);
+        const uint32_t nsp = st->last_nspec, cur = st->cur;
+        const uint32_t b = pblk[qq];
         if (b == NONE) continue;
-        const VolDev &V = vols[q.vol];
-        uint32_t vi = V.vis_idx[bidx(V, b)];
+        const uint32_t vi = V.vis_idx[bidx(V, b)];
+        const uint32_t pix = (cur ? act1 : act)[qq / nsp];
         if (vi >= vadm) continue;
-        uint32_t dst = W.vis_off[vi] + W.pair_rank[x];
-        const ReqState *st = q.st;
-        uint32_t i = qq / st->last_nspec;
-        uint32_t pix = q.act[st->cur][i];
+        const uint32_t dst = W.vis_off[vi] + rank;
         W.s_ray[dst] = (r << 24) | pix;
         W.s_q[dst] = qq;
         W.s_vi[dst] = vi;
