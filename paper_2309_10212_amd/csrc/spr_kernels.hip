@@ -2,11 +2,11 @@
 //
 // Load path (Sec. 3.1): block decode + value range, fine and coarse macrocell
 // grids.  Per pass (Sec. 3 pipeline (a)-(f) with the Sec. 4 speculation
-// changes): pass set-up, speculative two-level traversal with visible-block
-// dedupe, mark active blocks, cache lookup + per-block pair-run allocation,
-// LRU eviction (only when the free list runs short), slot assignment, miss
-// decode + pair scatter, block raytrace, depth composite, ray counting and
-// ordered compaction with the N_spec update.
+// changes): pass set-up, speculative two-level traversal, visible-block
+// dedupe with pair ranks, active-block marking with the cache lookup and the
+// per-block pair-run allocation, LRU eviction (only when the free list runs
+// short), slot assignment + pair scatter, miss decode, block raytrace, depth
+// composite, ray counting and ordered compaction with the N_spec update.
 #include "spr_launch.h"
 #include "spr_codec.h"
 
