@@ -68,7 +68,7 @@ typedef struct {
     int device;            /* HIP device ordinal */
     void *stream;          /* hipStream_t; NULL = null stream */
     size_t cache_bytes;    /* decoded-block cache capacity; 256 B per slot (Sec. 3.5) */
-    uint32_t spec_cap;     /* default speculation cap for new renders (Sec. 4: 64); 0 -> 64 */
+    uint32_t spec_cap;     /* default speculation cap for new renders (Sec. 4: 64); 0 -> 64; at most 4096 */
     uint32_t flags;        /* reserved, must be 0 */
     spr_allocator alloc;   /* optional; alloc.alloc == NULL -> hipMalloc/hipFree */
 } spr_config;

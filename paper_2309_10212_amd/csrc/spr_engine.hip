@@ -377,6 +377,7 @@ spr_status spr_ctx_create(const spr_config *cfg, spr_ctx **out) {
     if (!cfg || !out) return fail(SPR_E_INVALID, "null argument");
     *out = nullptr;
     if (cfg->flags != 0) return fail(SPR_E_INVALID, "flags must be 0");
+    if (cfg->spec_cap > 4096) return fail(SPR_E_INVALID, "spec cap must be in 1..4096 (0 for the default)");
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (cfg->device < 0 || cfg->device >= ndev) return fail(SPR_E_INVALID, "device %d out of range", cfg->device);
@@ -729,6 +730,7 @@ static void free_render_buffers(spr_ctx *c, spr_render *r) {
     dfree(c, q.act[1], n);
     dfree(c, q.pair_blk, n);
     dfree(c, q.rgbz, n);
+    dfree(c, q.best, n);
     dfree(c, q.image, n);
     dfree(c, q.hits, n);
     dfree(c, r->d_st, 1);
@@ -769,6 +771,7 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
         if ((st = dalloc(c, npix, &q.act[1])) != SPR_OK) break;
         if ((st = dalloc(c, npix, &q.pair_blk)) != SPR_OK) break;
         if ((st = dalloc(c, npix, &q.rgbz)) != SPR_OK) break;
+        if ((st = dalloc(c, npix, &q.best)) != SPR_OK) break;
         if ((st = dalloc(c, npix, &q.image)) != SPR_OK) break;
         if ((st = dalloc(c, npix, &q.hits)) != SPR_OK) break;
         if ((st = dalloc(c, 1, &r->d_st)) != SPR_OK) break;
@@ -797,6 +800,7 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     hipError_t e = hipMemcpy(r->d_st, &s0, sizeof(s0), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r->table.hdr, &one, sizeof(one), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r->d_req, &q, sizeof(q), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_fill_u64(c->stream, q.best, npix, ~0ull);
     hipEvent_t *pev = nullptr;
     if (e == hipSuccess && c->prof && prof_begin(c, 5, INIT_SLOTS, &pev) != SPR_OK) e = hipErrorUnknown;
     if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols, r->cwords, pev);

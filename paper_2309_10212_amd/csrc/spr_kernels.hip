@@ -1165,7 +1165,17 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
                 if (tx > R.tx || !advance(R, L1, c, tx, lo, hi)) break;
                 t0 = tx;
             }
-            q.rgbz[qq] = out;
+            if (out.cell != NONE) {
+                // The pair's slot k within its ray orders the ray's hits as t
+                // does (slots follow the traversal; ties go to the earlier
+                // block), so the composite's first hit in slot order is the
+                // minimum of slot << 38 | cell << 32 | rgba over the ray's
+                // hits (k < 4096).  Only hits write their record (for t).
+                const uint32_t k = qq % q.st->last_nspec;
+                const uint64_t key = ((uint64_t)k << 38) | ((uint64_t)out.cell << 32) | out.rgba;
+                __hip_atomic_fetch_min(as_global(q.best) + pix, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                q.rgbz[qq] = out;
+            }
         }
         __syncthreads();   // the next tile reuses the LDS
     }
@@ -1203,6 +1213,11 @@ __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const 
             const Rgbz *res = q.rgbz + (size_t)i * ns;
             uint32_t last = NONE;
             bool term = false, stopped = false;
+            // this pass's first hit in slot order (the raytrace's atomic
+            // minimum), reset for the next pass
+            const uint64_t best = q.best[pix];
+            if (best != ~0ull) q.best[pix] = ~0ull;
+            const uint32_t kb = best != ~0ull ? (uint32_t)(best >> 38) : NONE;
             for (uint32_t k = 0; k < ns; ++k) {
                 uint32_t b = slots[k];
                 if (b == NONE) {
@@ -1220,13 +1235,12 @@ __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const 
                     my_def++;
                     continue;
                 }
-                Rgbz rec = res[k];
-                if (rec.t < __builtin_inf()) {
-                    image[pix] = rec.rgba;
+                if (k == kb) {
+                    image[pix] = (uint32_t)best;
                     spr_hit h;
-                    h.t = rec.t;
+                    h.t = res[k].t;
                     h.block_id = b;
-                    h.cell = rec.cell;
+                    h.cell = (uint32_t)(best >> 32) & 63u;
                     hits[pix] = h;
                     term = true;
                     continue;
