@@ -43,6 +43,20 @@ def test_error_paths_without_gpu():
     assert lib.spr_batch_free(None) == -1
 
 
+def test_config_is_validated_before_any_device_call():
+    from paper_2309_10212_amd import spr
+    lib = spr.load_library()
+    out = ctypes.c_void_p()
+    cfg = spr._Config()
+    cfg.device, cfg.cache_bytes, cfg.flags = 0, 1 << 20, 1
+    assert lib.spr_ctx_create(ctypes.byref(cfg), ctypes.byref(out)) == -1
+    assert b"flags" in lib.spr_last_error()
+    cfg.flags, cfg.spec_cap = 0, 4097   # a hit's slot is packed into 12 bits
+    assert lib.spr_ctx_create(ctypes.byref(cfg), ctypes.byref(out)) == -1
+    assert b"spec cap" in lib.spr_last_error()
+    assert not out.value
+
+
 def test_struct_layouts_match_header():
     from paper_2309_10212_amd import spr
     assert ctypes.sizeof(spr.PassStats) == 56
