@@ -13,7 +13,7 @@ initial rays, then run passes (speculative traversal, mark, cache update and
 decode, pair build, block raytrace, composite, compaction) until every ray has
 terminated.  Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one
+Prints one JSON line.  --gpus N with N > 1 is refused: libspr runs on one
 GPU.
 """
 from __future__ import annotations
@@ -193,7 +193,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus N > 1 is not supported",
+        print(json.dumps({"error": "libspr runs on exactly one GPU; --gpus N > 1 is not supported",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
@@ -405,7 +405,7 @@ def main():
             "bytes": int(sum(i["bcmc_blocks"] for i in infos) / len(infos) * 256),
             "cache_bytes_needed": int(dc["max_active_blocks"] * 256),
             "note": "blocks whose fine range contains the isovalue (what decompressing every block that may hold "
-                    "the surface decodes) vs blocks this build decoded per view, with the block cache warm across "
+                    "the surface decodes) vs blocks the speculative renderer decoded per view, with the block cache warm across "
                     "the orbit; bytes at 256 B per decoded block vs the largest per-pass active set"},
         "batched": batched,
         "sweep": sweep,
