@@ -130,7 +130,7 @@ struct ReqDev {
     uint32_t *pair_blk;         // per pair slot (R_BID of Sec. 3.3/4.1)
     Rgbz *rgbz;                 // per pair slot (written for hits only)
     uint64_t *best;             // per pixel: minimum over this pass's hits of
-                                // slot << 38 | cell << 32 | rgba, ~0 for none
+                                // pair slot << 38 | cell << 32 | rgba, ~0 for none
     uint32_t *image;            // RGBA8 per pixel
     spr_hit *hits;              // per pixel
     ReqState *st;

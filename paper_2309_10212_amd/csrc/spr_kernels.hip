@@ -1166,13 +1166,12 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
                 t0 = tx;
             }
             if (out.cell != NONE) {
-                // The pair's slot k within its ray orders the ray's hits as t
-                // does (slots follow the traversal; ties go to the earlier
-                // block), so the composite's first hit in slot order is the
-                // minimum of slot << 38 | cell << 32 | rgba over the ray's
-                // hits (k < 4096).  Only hits write their record (for t).
-                const uint32_t k = qq % q.st->last_nspec;
-                const uint64_t key = ((uint64_t)k << 38) | ((uint64_t)out.cell << 32) | out.rgba;
+                // A ray's pair slots are consecutive and follow its traversal,
+                // so the pair slot orders the ray's hits as t does (ties go to
+                // the earlier block): the composite's first hit in slot order
+                // is the minimum of slot << 38 | cell << 32 | rgba over the
+                // ray's hits (slots < 2^24).  Only hits write their record (t).
+                const uint64_t key = ((uint64_t)qq << 38) | ((uint64_t)out.cell << 32) | out.rgba;
                 __hip_atomic_fetch_min(as_global(q.best) + pix, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 q.rgbz[qq] = out;
             }
@@ -1217,7 +1216,7 @@ __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const 
             // minimum), reset for the next pass
             const uint64_t best = q.best[pix];
             if (best != ~0ull) q.best[pix] = ~0ull;
-            const uint32_t kb = best != ~0ull ? (uint32_t)(best >> 38) : NONE;
+            const uint32_t kb = best != ~0ull ? (uint32_t)(best >> 38) - i * ns : NONE;   // slot within the ray
             for (uint32_t k = 0; k < ns; ++k) {
                 uint32_t b = slots[k];
                 if (b == NONE) {

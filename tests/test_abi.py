@@ -51,7 +51,7 @@ def test_config_is_validated_before_any_device_call():
     cfg.device, cfg.cache_bytes, cfg.flags = 0, 1 << 20, 1
     assert lib.spr_ctx_create(ctypes.byref(cfg), ctypes.byref(out)) == -1
     assert b"flags" in lib.spr_last_error()
-    cfg.flags, cfg.spec_cap = 0, 4097   # a hit's slot is packed into 12 bits
+    cfg.flags, cfg.spec_cap = 0, 4097   # beyond the documented 1..4096
     assert lib.spr_ctx_create(ctypes.byref(cfg), ctypes.byref(out)) == -1
     assert b"spec cap" in lib.spr_last_error()
     assert not out.value
