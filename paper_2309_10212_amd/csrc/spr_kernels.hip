@@ -59,6 +59,16 @@ __global__ __launch_bounds__(64) void k_decode_ids(VolDev V, const uint32_t *ids
     }
 }
 
+// Coordinates of linear index v in a grid n0 wide and n1 deep, in 32-bit
+// arithmetic (block and coarse-cell counts are below 2^32; a 64-bit division
+// costs about a hundred instructions).
+__device__ __forceinline__ void unravel3(uint32_t v, uint32_t n0, uint32_t n1, int &x, int &y, int &z) {
+    const uint32_t r = v / n0;
+    x = (int)(v - r * n0);
+    y = (int)(r % n1);
+    z = (int)(r / n1);
+}
+
 // Load path: decode every block once and keep only its value range over the
 // samples inside the volume (Sec. 3.1).
 template <int RWMAX>
@@ -69,9 +79,8 @@ __global__ __launch_bounds__(64) void k_block_ranges(VolDev V, float2 *blk) {
     __syncthreads();
     for (uint64_t b = blockIdx.x * 64ull + lane; b < V.nblocks; b += (uint64_t)gridDim.x * 64) {
         const uint32_t *rec = V.stream + b * (uint64_t)V.rec_words;
-        int bx = (int)(b % (uint64_t)V.nb[0]);
-        int by = (int)((b / (uint64_t)V.nb[0]) % (uint64_t)V.nb[1]);
-        int bz = (int)(b / ((uint64_t)V.nb[0] * V.nb[1]));
+        int bx, by, bz;
+        unravel3((uint32_t)b, (uint32_t)V.nb[0], (uint32_t)V.nb[1], bx, by, bz);
         int ex = V.n[0] - 4 * bx, ey = V.n[1] - 4 * by, ez = V.n[2] - 4 * bz;   // samples inside, per axis
         float lo = __builtin_inff(), hi = -__builtin_inff();
         if (V.rate == 32) {
@@ -118,9 +127,8 @@ __global__ void k_fine_grid(VolDev V) {
     const float2 *blk = V.blk;
     uint64_t nb = V.nblocks;
     for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < nb; b += (uint64_t)gridDim.x * blockDim.x) {
-        int bx = (int)(b % (uint64_t)V.nb[0]);
-        int by = (int)((b / (uint64_t)V.nb[0]) % (uint64_t)V.nb[1]);
-        int bz = (int)(b / ((uint64_t)V.nb[0] * V.nb[1]));
+        int bx, by, bz;
+        unravel3((uint32_t)b, (uint32_t)V.nb[0], (uint32_t)V.nb[1], bx, by, bz);
         float lo = __builtin_inff(), hi = -__builtin_inff();
         for (int dz = 0; dz < 2; ++dz)
             for (int dy = 0; dy < 2; ++dy)
@@ -139,9 +147,8 @@ __global__ void k_fine_grid(VolDev V) {
 __global__ void k_coarse_grid(VolDev V) {
     uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nc; c += (uint64_t)gridDim.x * blockDim.x) {
-        int cx = (int)(c % (uint64_t)V.nc[0]);
-        int cy = (int)((c / (uint64_t)V.nc[0]) % (uint64_t)V.nc[1]);
-        int cz = (int)(c / ((uint64_t)V.nc[0] * V.nc[1]));
+        int cx, cy, cz;
+        unravel3((uint32_t)c, (uint32_t)V.nc[0], (uint32_t)V.nc[1], cx, cy, cz);
         float lo = __builtin_inff(), hi = -__builtin_inff();
         for (int z = 4 * cz; z < 4 * cz + 4 && z < V.nb[2]; ++z)
             for (int y = 4 * cy; y < 4 * cy + 4 && y < V.nb[1]; ++y)
@@ -322,9 +329,8 @@ __global__ __launch_bounds__(256) void k_iso_masks(Table T, const VolDev *vols) 
         uint64_t bits = 0;
         float2 cr = V.coarse[c];
         if (cr.x <= iso && iso <= cr.y) {
-            int cx = (int)(c % (uint64_t)V.nc[0]);
-            int cy = (int)((c / (uint64_t)V.nc[0]) % (uint64_t)V.nc[1]);
-            int cz = (int)(c / ((uint64_t)V.nc[0] * V.nc[1]));
+            int cx, cy, cz;
+            unravel3((uint32_t)c, (uint32_t)V.nc[0], (uint32_t)V.nc[1], cx, cy, cz);
             for (int i = 0; i < 64; ++i) {
                 int x = 4 * cx + (i & 3), y = 4 * cy + ((i >> 2) & 3), z = 4 * cz + (i >> 4);
                 if (x >= V.nb[0] || y >= V.nb[1] || z >= V.nb[2]) continue;
@@ -365,7 +371,7 @@ __global__ __launch_bounds__(256) void k_cdist_pass(Table T, const VolDev *vols,
     const int n_a = V.nc[axis];
     const uint64_t stride = axis == 0 ? 1ull : (axis == 1 ? (uint64_t)V.nc[0] : (uint64_t)V.nc[0] * V.nc[1]);
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nc; c += (uint64_t)gridDim.x * blockDim.x) {
-        const int p = (int)((c / stride) % (uint64_t)n_a);
+        const int p = (int)(((uint32_t)c / (uint32_t)stride) % (uint32_t)n_a);
         int best = CD_MAX;
         for (int k = -CD_MAX; k <= CD_MAX; ++k) {
             const int pk = p + k;
