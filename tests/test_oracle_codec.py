@@ -104,3 +104,149 @@ def test_stream_size_validation():
     s = volgen.encode(vol, 4)
     with pytest.raises(RuntimeError):
         oracle.decode_volume(s[:-1], (8, 8, 8), 4)
+
+
+# ------------------------------------------------------------------ golden --
+# A record written bit by bit from the format description, whose inverse
+# transform overflows 32 bits; the expected samples were worked out by hand
+# (tests/golden/codec_wrap_record.json holds the bit segments and the
+# derivation).  It pins the decoder's 32-bit wrapping inverse-transform rule.
+
+def _golden():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "codec_wrap_record.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _pack_bits(segments, nbits):
+    bits = []
+    for seg in segments:
+        bits += [int(ch) for ch in seg["bits"]] * int(seg.get("repeat", 1))
+    assert len(bits) <= nbits
+    words = np.zeros(nbits // 32, np.uint32)
+    for i, b in enumerate(bits):
+        if b:
+            words[i >> 5] |= np.uint32(1 << (i & 31))
+    return words, len(bits)
+
+
+def test_golden_record_bits_match_their_segments():
+    g = _golden()
+    words, used = _pack_bits(g["bit_segments"], 64 * g["rate_bits"])
+    assert used == 167
+    assert [int(w, 16) for w in g["record_words_hex"]] == [int(w) for w in words]
+
+
+def test_golden_record_wraps_in_32_bits():
+    g = _golden()
+    rec = np.array([int(w, 16) for w in g["record_words_hex"]], np.uint32)
+    out = oracle.decode_block(rec.view(np.uint8), g["rate_bits"])
+    want = np.array(g["expected_values"], np.float32)
+    assert np.array_equal(out, want), np.nonzero(out != want)
+    # the integers before scaling, as derived by hand (e = 0: value = q * 2^-27)
+    q = np.array(g["expected_q"], np.int64)
+    assert np.array_equal((q.astype(np.float64) * 2.0 ** -27).astype(np.float32), want)
+    # the corner the wrap decides: -12 with the 32-bit rule, +20 without it
+    assert out.reshape(4, 4, 4)[3, 3, 3] == np.float32(-12.0)
+
+
+# -------------------------------------------------------------- truncation --
+# Fixed rate means the record of block b is the first 64R bits of the
+# embedded code.  These pin where the decoder stops and that it uses every
+# bit up to there:
+#   - the encoder's rate-R record is the first 64R bits of its rate-16 record
+#     (embedded coding), so encoder and decoder cannot share an off-by-one at
+#     the budget without this failing;
+#   - the decoder reads nothing past 64R bits (changing the next record
+#     changes nothing) and does read bit 64R-1 (flipping it changes the output
+#     of some blocks);
+#   - a block whose complete code fits in 64R bits decodes at rate R to the
+#     block-floating-point quantisation of its values, computed here with
+#     numpy from the format's definition (frexp exponent, truncation to 27
+#     fraction bits).
+
+def _bits(words):
+    w = np.asarray(words, np.uint32)
+    return ((w[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1).astype(np.uint8).reshape(-1)
+
+
+def _blocks(seed, n):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        kind = i % 5
+        if kind == 4:
+            # constant blocks of a few significant bits: codes short enough for rate 1
+            v = np.full(64, float(rng.choice([1, 3, 5, -7, -1])) * 2.0 ** int(rng.integers(-20, 20)))
+            v[int(rng.integers(0, 64))] *= float(rng.choice([1.0, 1.0, 0.5]))
+        elif kind == 0:
+            v = rng.standard_normal(64)
+        elif kind == 1:
+            v = np.cumsum(rng.standard_normal(64)) * 0.1 + 3.0
+        elif kind == 2:
+            v = np.zeros(64)
+            idx = rng.choice(64, rng.integers(1, 6), replace=False)
+            v[idx] = rng.integers(-6, 7, len(idx)) * 0.125
+        else:
+            v = np.sin(np.arange(64) * rng.uniform(0.05, 0.5)) * 10.0 ** rng.uniform(-3, 3)
+        out.append(v.astype(np.float32))
+    return out
+
+
+@pytest.mark.parametrize("rate", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_rate_r_record_is_prefix_of_rate16_record(rate):
+    for v in _blocks(100 + rate, 64):
+        r16 = _bits(np.frombuffer(volgen.encode_block(v, 16).tobytes(), np.uint32))
+        rr = _bits(np.frombuffer(volgen.encode_block(v, rate).tobytes(), np.uint32))
+        assert len(rr) == 64 * rate
+        assert np.array_equal(rr, r16[:64 * rate])
+
+
+@pytest.mark.parametrize("rate", [1, 2, 4, 8])
+def test_decoder_stops_exactly_at_the_budget(rate):
+    nwords = 2 * rate
+    changed = 0
+    rng = np.random.default_rng(rate)
+    for v in _blocks(200 + rate, 96):
+        rec = np.frombuffer(volgen.encode_block(v, rate).tobytes(), np.uint32).copy()
+        base = oracle.decode_block(rec.view(np.uint8), rate)
+        # the next record's bits: zeros or random ones, never read
+        tail = rng.integers(0, 2**32, nwords, dtype=np.uint64).astype(np.uint32)
+        two = np.concatenate([rec, tail])
+        s = two.view(np.uint8)
+        dec = oracle.decode_blocks(s, (8, 4, 4), rate, np.array([0], np.uint32))[0]
+        assert np.array_equal(dec, base)
+        # the last bit of the record is read: flip it
+        flip = rec.copy()
+        flip[-1] ^= np.uint32(1 << 31)
+        out = oracle.decode_block(flip.view(np.uint8), rate)
+        changed += not np.array_equal(out, base)
+    assert changed >= 4, changed   # a decoder stopping one bit early changes none
+
+
+def _quantised(v):
+    v = v.astype(np.float32)
+    m = float(np.max(np.abs(v.astype(np.float64))))
+    if m == 0.0:
+        return np.zeros(64, np.float32)
+    e = max(np.frexp(m)[1], -127)
+    q = np.trunc(v.astype(np.float64) * 2.0 ** (27 - e))
+    return (q * 2.0 ** (e - 27)).astype(np.float32)
+
+
+@pytest.mark.parametrize("rate", [1, 2, 3, 4, 6, 8])
+def test_complete_code_within_budget_decodes_to_the_quantisation(rate):
+    fits = 0
+    for v in _blocks(300 + rate, 200):
+        r16 = _bits(np.frombuffer(volgen.encode_block(v, 16).tobytes(), np.uint32))
+        # a rate-16 code that ended well before its budget and needs no bit
+        # past 64R: the whole code fits in the rate-R record
+        if r16[64 * rate:].any() or r16[512:].any():
+            continue
+        rec = volgen.encode_block(v, rate)
+        out = oracle.decode_block(rec, rate)
+        assert np.array_equal(out, _quantised(v)), (rate, np.nonzero(out != _quantised(v)))
+        fits += 1
+    assert fits >= 10, fits

@@ -41,6 +41,18 @@
  *                  negative); bit 0 ends the plane; no test is written when
  *                  no candidate is left.  Writing stops when 64R bits are
  *                  used; the rest of the record is zero.
+ *     decoding   : read the planes back (a record ends after 64R bits, so a
+ *                  truncated code leaves the remaining bits 0), undo the
+ *                  order, invert each line as l1 = L - floor(H/2),
+ *                  l0 = l1 + H, a1 = l0 - floor(h0/2), a0 = a1 + h0,
+ *                  a3 = l1 - floor(h1/2), a2 = a3 + h1, along z, then y,
+ *                  then x, in 32-bit two's-complement arithmetic (sums wrap
+ *                  modulo 2^32), and output float(q * 2^(e-27)) rounded once.
+ *                  The wrap can only matter for records this encoder never
+ *                  writes (its coefficients keep every partial sum below
+ *                  2^31); the rule was fixed after the first decoders were
+ *                  written, without a version change, since it changes no
+ *                  encoder output.
  */
 #include <math.h>
 #include <stdint.h>
