@@ -134,6 +134,9 @@ typedef struct {
     uint64_t pair_slots;      /* sum over passes of N_act * N_spec (R_BID entries written) */
     uint64_t served_pairs;    /* sum over passes of pairs raytraced */
     uint64_t max_active_blocks; /* largest active-block count of any pass: the cache slots a pass needed */
+    uint64_t walk_guard;      /* ray walks (traversal or block raytrace) ended by a step guard instead of
+                                 by leaving the domain, the block, or finding their blocks; every step
+                                 advances a cell index, so this is 0 unless the walk logic is broken */
 } spr_counters;
 
 /* Per-render summary. */
@@ -155,11 +158,36 @@ typedef struct {
     uint64_t launches;
 } spr_kernel_time;
 
+/* Device memory by what it holds (Sec. 5.3 reports total and cache memory).
+ * Kinds: SPR_MEM_COMPRESSED (compressed streams), SPR_MEM_GRIDS (macrocell
+ * grids and per-block state: fine and coarse ranges, block-to-slot map, pair
+ * counters, visible index, active stamps), SPR_MEM_RAYS (per-render buffers:
+ * ray state, active lists, pair slots, hit records, image, hit buffer,
+ * isovalue masks and empty-space distances), SPR_MEM_CACHE (the decoded-block
+ * cache: 256-byte slots, owners, LRU stamps, free stack), SPR_MEM_SCRATCH
+ * (pass workspace, control block, batch tables, debug staging). */
+#define SPR_MEM_COMPRESSED 0
+#define SPR_MEM_GRIDS 1
+#define SPR_MEM_RAYS 2
+#define SPR_MEM_CACHE 3
+#define SPR_MEM_SCRATCH 4
+#define SPR_MEM_KINDS 5
+typedef struct {
+    size_t current[SPR_MEM_KINDS];   /* bytes held now, by kind */
+    size_t at_peak[SPR_MEM_KINDS];   /* bytes by kind at the moment the total peaked (they sum to peak) */
+    size_t kind_peak[SPR_MEM_KINDS]; /* each kind's own high-water mark */
+    size_t total, peak;              /* as spr_mem_stats */
+} spr_mem_split;
+
 /* ---------------------------------------------------------------- context */
 spr_status spr_ctx_create(const spr_config *cfg, spr_ctx **out);
 spr_status spr_ctx_destroy(spr_ctx *ctx);
 /* Device bytes currently held by the context and its objects, and the peak. */
 spr_status spr_mem_stats(spr_ctx *ctx, size_t *current, size_t *peak);
+/* The same bytes split by kind (see spr_mem_split).  With reset_peak != 0 the
+ * peaks are set to the current values after they are reported, so that a
+ * later call reports the peak of what ran in between.  No device call. */
+spr_status spr_mem_split_get(spr_ctx *ctx, spr_mem_split *out, int reset_peak);
 /* Cumulative counters (synchronises). */
 spr_status spr_ctx_counters(spr_ctx *ctx, spr_counters *out);
 /* Profiling mode: when enabled, passes run eagerly (not from a captured
@@ -205,8 +233,12 @@ spr_status spr_volume_build_grids(spr_volume *vol);
  * fine_count / coarse_count pairs (NULL to skip).  Synchronises. */
 spr_status spr_volume_ranges(spr_volume *vol, float *fine_lohi, size_t fine_count, float *coarse_lohi,
                              size_t coarse_count);
-/* Debug/parity: decode n listed blocks with the device decoder into
- * host_out[i*64 .. i*64+63] (raster order x + 4y + 16z).  Synchronises. */
+/* Debug/parity: decode n listed blocks with the device decoder (the block
+ * decompression of Sec. 3.5, run outside a pass) into host_out[i*64 ..
+ * i*64+63] (raster order x + 4y + 16z).  ids and host_out are host arrays of
+ * n entries and n*64 floats, owned by the caller.  SPR_E_INVALID for an id
+ * outside the volume; device staging comes from the context's allocator
+ * (SPR_E_OOM if it fails).  Synchronises. */
 spr_status spr_debug_decode_blocks(spr_volume *vol, const uint32_t *ids, uint32_t n, float *host_out);
 
 /* Debug/parity: sqrt(x[i]) and x[i] / y[i] in fp64 on the device, compiled
@@ -232,7 +264,9 @@ spr_status spr_render_set_spec_cap(spr_render *r, uint32_t cap);
  * render does nothing.  With opt_stats != NULL the call synchronises and
  * fills the counters. */
 spr_status spr_render_pass(spr_render *r, spr_pass_stats *opt_stats);
-/* Synchronise and report whether every ray has terminated (N_act == 0). */
+/* Synchronise and report whether every ray has terminated: the count of
+ * active rays after the last pass (Sec. 3 step (f) counts the rays still
+ * active; the render is complete when none is left) is 0. */
 spr_status spr_render_done(spr_render *r, int *done);
 /* Run passes until done or max_passes; *passes_run = passes executed.
  * Synchronises. */
@@ -240,7 +274,12 @@ spr_status spr_render_run(spr_render *r, uint32_t max_passes, uint32_t *passes_r
 /* Summary of a render (synchronises). */
 spr_status spr_render_get_info(spr_render *r, spr_render_info *out);
 /* Copy the RGBA8 image (w*h*4 bytes, row 0 at the top, r in the low byte)
- * or the hit buffer (w*h records) to host memory.  Synchronises. */
+ * or the hit buffer (w*h records) to host memory.  The image after any pass
+ * is the progressive partial image (Sec. 3: pixels whose rays have
+ * terminated are final, the rest are background); the hit buffer holds
+ * each finished ray's hit (Sec. 3.7: parameter t, the hit block and the dual
+ * cell within it).  bytes / count must equal w*h*4 / w*h (SPR_E_INVALID
+ * otherwise); the caller owns the buffers.  Synchronises. */
 spr_status spr_read_image(spr_render *r, uint8_t *rgba, size_t bytes);
 spr_status spr_read_hits(spr_render *r, spr_hit *hits, size_t count);
 /* Device pointers of the image (uint32 RGBA per pixel) and hit buffer; valid

@@ -35,12 +35,14 @@ class Choice:
 
 def run_batch(ctx, vols, reqs, spec_cap: int, poll_every: int = 2):
     """Render reqs (objects with .vol .cam .iso .w .h) as one batch to completion.
-    Returns (seconds, rays entered, passes, renders) - renders still allocated."""
+    Returns (seconds, rays entered, passes, renders) - renders still allocated.
+    The clock runs from before the first render's set-up (initial rays and
+    isovalue masks) to the last pass, as a plain render's clock would."""
     import torch
-    renders = [spr.Render(vols[q.vol], q.cam, q.iso, q.w, q.h, spec_cap=spec_cap) for q in reqs]
-    b = spr.Batch(ctx, renders)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    renders = [spr.Render(vols[q.vol], q.cam, q.iso, q.w, q.h, spec_cap=spec_cap) for q in reqs]
+    b = spr.Batch(ctx, renders)
     passes = b.run(poll_every=poll_every)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0

@@ -46,6 +46,16 @@ spr_status fail(spr_status st, const char *fmt, ...) {
 
 uint32_t round64h(uint64_t x) { return (uint32_t)((x + 63u) & ~63ull); }
 
+// What a device allocation holds (spr_mem_split reports bytes per kind).
+enum MemCat {
+    MEM_COMPRESSED = 0,   // compressed streams
+    MEM_GRIDS,            // macrocell grids and per-block state
+    MEM_RAYS,             // per-render buffers: rays, pair slots, image, hits, masks
+    MEM_CACHE,            // decoded-block cache
+    MEM_SCRATCH,          // pass workspace, control block, batch tables, debug staging
+    MEM_NCAT
+};
+
 }  // namespace
 
 struct spr_ctx {
@@ -55,6 +65,7 @@ struct spr_ctx {
     uint32_t spec_cap = 64;
     uint32_t rt_tile = 256, rt_lb = 32;   // raytrace launch tuning (spr_ctx_set_tuning)
     size_t mem_cur = 0, mem_peak = 0;
+    size_t mem_cat[MEM_NCAT] = {}, mem_cat_peak[MEM_NCAT] = {}, mem_at_peak[MEM_NCAT] = {};
     PassCtl *ctl = nullptr;
     VolDev *d_vols = nullptr;
     VolDev h_vols[MAX_VOLUMES];
@@ -127,7 +138,7 @@ namespace {
 
 // ------------------------------------------------------------- memory ------
 
-spr_status dev_alloc(spr_ctx *c, size_t bytes, void **out) {
+spr_status dev_alloc(spr_ctx *c, MemCat cat, size_t bytes, void **out) {
     *out = nullptr;
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~(size_t)255;
@@ -143,12 +154,17 @@ spr_status dev_alloc(spr_ctx *c, size_t bytes, void **out) {
         }
     }
     c->mem_cur += bytes;
-    if (c->mem_cur > c->mem_peak) c->mem_peak = c->mem_cur;
+    c->mem_cat[cat] += bytes;
+    if (c->mem_cat[cat] > c->mem_cat_peak[cat]) c->mem_cat_peak[cat] = c->mem_cat[cat];
+    if (c->mem_cur > c->mem_peak) {
+        c->mem_peak = c->mem_cur;
+        for (int k = 0; k < MEM_NCAT; ++k) c->mem_at_peak[k] = c->mem_cat[k];
+    }
     *out = p;
     return SPR_OK;
 }
 
-void dev_free(spr_ctx *c, void *p, size_t bytes) {
+void dev_free(spr_ctx *c, MemCat cat, void *p, size_t bytes) {
     if (!p) return;
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~(size_t)255;
@@ -158,19 +174,20 @@ void dev_free(spr_ctx *c, void *p, size_t bytes) {
         (void)hipFree(p);
     }
     c->mem_cur -= bytes;
+    c->mem_cat[cat] -= bytes;
 }
 
 template <typename T>
-spr_status dalloc(spr_ctx *c, size_t count, T **out) {
+spr_status dalloc(spr_ctx *c, MemCat cat, size_t count, T **out) {
     void *p;
-    CHK(dev_alloc(c, count * sizeof(T), &p));
+    CHK(dev_alloc(c, cat, count * sizeof(T), &p));
     *out = (T *)p;
     return SPR_OK;
 }
 
 template <typename T>
-void dfree(spr_ctx *c, T *&p, size_t count) {
-    dev_free(c, (void *)p, count * sizeof(T));
+void dfree(spr_ctx *c, MemCat cat, T *&p, size_t count) {
+    dev_free(c, cat, (void *)p, count * sizeof(T));
     p = nullptr;
 }
 
@@ -240,42 +257,42 @@ spr_status ensure_work(spr_ctx *c, uint64_t P) {
     HIPCHK(hipStreamSynchronize(c->stream));
     Work &W = c->work;
     size_t oP = W.cap_P, oK = W.cap_K;
-    dfree(c, W.vis_list, oP); dfree(c, W.vis_off, oP);
-    dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
-    dfree(c, W.pair_rank, oP); dfree(c, W.s_ray, oP); dfree(c, W.s_q, oP); dfree(c, W.s_vi, oP);
-    dfree(c, W.vis_nsl, 8 * oP);
+    dfree(c, MEM_SCRATCH, W.vis_list, oP); dfree(c, MEM_SCRATCH, W.vis_off, oP);
+    dfree(c, MEM_SCRATCH, W.miss_list, oK); dfree(c, MEM_SCRATCH, W.miss_slot, oK);
+    dfree(c, MEM_SCRATCH, W.pair_rank, oP); dfree(c, MEM_SCRATCH, W.s_ray, oP); dfree(c, MEM_SCRATCH, W.s_q, oP); dfree(c, MEM_SCRATCH, W.s_vi, oP);
+    dfree(c, MEM_SCRATCH, W.vis_nsl, 8 * oP);
     W.cap_P = 0; W.cap_K = 0;
     uint64_t cP = P, cK = 8 * P;
-    CHK(dalloc(c, cP, &W.vis_list)); CHK(dalloc(c, cP, &W.vis_off));
-    CHK(dalloc(c, cK, &W.miss_list)); CHK(dalloc(c, cK, &W.miss_slot));
-    CHK(dalloc(c, cP, &W.pair_rank)); CHK(dalloc(c, cP, &W.s_ray)); CHK(dalloc(c, cP, &W.s_q));
-    CHK(dalloc(c, cP, &W.s_vi)); CHK(dalloc(c, 8 * cP, &W.vis_nsl));
+    CHK(dalloc(c, MEM_SCRATCH, cP, &W.vis_list)); CHK(dalloc(c, MEM_SCRATCH, cP, &W.vis_off));
+    CHK(dalloc(c, MEM_SCRATCH, cK, &W.miss_list)); CHK(dalloc(c, MEM_SCRATCH, cK, &W.miss_slot));
+    CHK(dalloc(c, MEM_SCRATCH, cP, &W.pair_rank)); CHK(dalloc(c, MEM_SCRATCH, cP, &W.s_ray)); CHK(dalloc(c, MEM_SCRATCH, cP, &W.s_q));
+    CHK(dalloc(c, MEM_SCRATCH, cP, &W.s_vi)); CHK(dalloc(c, MEM_SCRATCH, 8 * cP, &W.vis_nsl));
     W.cap_P = (uint32_t)cP;
     W.cap_K = (uint32_t)cK;
     c->work_gen++;
     return SPR_OK;
 }
 
-spr_status alloc_table(spr_ctx *c, uint32_t cap, uint64_t max_A, uint64_t max_P, Table &T) {
+spr_status alloc_table(spr_ctx *c, MemCat cat, uint32_t cap, uint64_t max_A, uint64_t max_P, Table &T) {
     T.cap = cap;
     T.max_A = (uint32_t)max_A;
     T.max_P = (uint32_t)max_P;
-    CHK(dalloc(c, 1, &T.hdr));
-    CHK(dalloc(c, cap + 1, &T.act_base));
-    CHK(dalloc(c, cap + 1, &T.pair_base));
-    CHK(dalloc(c, cap + 1, &T.trav_base));
-    CHK(dalloc(c, max_A / 64 + 2, &T.wave_rec));
-    CHK(dalloc(c, max_A / 64 + 2, &T.wave_off));
+    CHK(dalloc(c, cat, 1, &T.hdr));
+    CHK(dalloc(c, cat, cap + 1, &T.act_base));
+    CHK(dalloc(c, cat, cap + 1, &T.pair_base));
+    CHK(dalloc(c, cat, cap + 1, &T.trav_base));
+    CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_rec));
+    CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_off));
     return SPR_OK;
 }
 
-void free_table(spr_ctx *c, Table &T) {
-    dfree(c, T.hdr, 1);
-    dfree(c, T.act_base, T.cap + 1);
-    dfree(c, T.pair_base, T.cap + 1);
-    dfree(c, T.trav_base, T.cap + 1);
-    dfree(c, T.wave_rec, T.max_A / 64 + 2);
-    dfree(c, T.wave_off, T.max_A / 64 + 2);
+void free_table(spr_ctx *c, MemCat cat, Table &T) {
+    dfree(c, cat, T.hdr, 1);
+    dfree(c, cat, T.act_base, T.cap + 1);
+    dfree(c, cat, T.pair_base, T.cap + 1);
+    dfree(c, cat, T.trav_base, T.cap + 1);
+    dfree(c, cat, T.wave_rec, T.max_A / 64 + 2);
+    dfree(c, cat, T.wave_off, T.max_A / 64 + 2);
 }
 
 spr_status set_table_count(spr_ctx *c, Table &T, uint32_t n) {
@@ -400,13 +417,13 @@ spr_status spr_ctx_create(const spr_config *cfg, spr_ctx **out) {
             return st;          \
         }                       \
     } while (0)
-    CTX_TRY(dalloc(c, 1, &c->ctl));
-    CTX_TRY(dalloc(c, MAX_VOLUMES, &c->d_vols));
+    CTX_TRY(dalloc(c, MEM_SCRATCH, 1, &c->ctl));
+    CTX_TRY(dalloc(c, MEM_SCRATCH, MAX_VOLUMES, &c->d_vols));
     c->cache.n_slots = (uint32_t)slots;
-    CTX_TRY(dalloc(c, slots * 64, &c->cache.slots));
-    CTX_TRY(dalloc(c, slots, &c->cache.owner));
-    CTX_TRY(dalloc(c, slots, &c->cache.stamp));
-    CTX_TRY(dalloc(c, slots, &c->cache.free_stack));
+    CTX_TRY(dalloc(c, MEM_CACHE, slots * 64, &c->cache.slots));
+    CTX_TRY(dalloc(c, MEM_CACHE, slots, &c->cache.owner));
+    CTX_TRY(dalloc(c, MEM_CACHE, slots, &c->cache.stamp));
+    CTX_TRY(dalloc(c, MEM_CACHE, slots, &c->cache.free_stack));
     if (hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
         spr_ctx_destroy(c);
         return fail(SPR_E_OOM, "pinned host allocation failed");
@@ -442,16 +459,17 @@ spr_status spr_ctx_destroy(spr_ctx *c) {
     if (c->stream || true) (void)hipStreamSynchronize(c->stream);
     Work &W = c->work;
     size_t oP = W.cap_P, oK = W.cap_K;
-    dfree(c, W.vis_list, oP); dfree(c, W.vis_off, oP);
-    dfree(c, W.miss_list, oK); dfree(c, W.miss_slot, oK);
-    dfree(c, W.pair_rank, oP); dfree(c, W.s_ray, oP); dfree(c, W.s_q, oP); dfree(c, W.s_vi, oP);
+    dfree(c, MEM_SCRATCH, W.vis_list, oP); dfree(c, MEM_SCRATCH, W.vis_off, oP);
+    dfree(c, MEM_SCRATCH, W.miss_list, oK); dfree(c, MEM_SCRATCH, W.miss_slot, oK);
+    dfree(c, MEM_SCRATCH, W.pair_rank, oP); dfree(c, MEM_SCRATCH, W.s_ray, oP); dfree(c, MEM_SCRATCH, W.s_q, oP); dfree(c, MEM_SCRATCH, W.s_vi, oP);
+    dfree(c, MEM_SCRATCH, W.vis_nsl, 8 * oP);
     size_t ns = c->cache.n_slots;
-    dfree(c, c->cache.slots, ns * 64);
-    dfree(c, c->cache.owner, ns);
-    dfree(c, c->cache.stamp, ns);
-    dfree(c, c->cache.free_stack, ns);
-    dfree(c, c->ctl, 1);
-    dfree(c, c->d_vols, MAX_VOLUMES);
+    dfree(c, MEM_CACHE, c->cache.slots, ns * 64);
+    dfree(c, MEM_CACHE, c->cache.owner, ns);
+    dfree(c, MEM_CACHE, c->cache.stamp, ns);
+    dfree(c, MEM_CACHE, c->cache.free_stack, ns);
+    dfree(c, MEM_SCRATCH, c->ctl, 1);
+    dfree(c, MEM_SCRATCH, c->d_vols, MAX_VOLUMES);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -467,6 +485,26 @@ spr_status spr_mem_stats(spr_ctx *c, size_t *current, size_t *peak) {
     if (!c) return fail(SPR_E_INVALID, "null context");
     if (current) *current = c->mem_cur;
     if (peak) *peak = c->mem_peak;
+    return SPR_OK;
+}
+
+spr_status spr_mem_split_get(spr_ctx *c, spr_mem_split *o, int reset_peak) {
+    if (!c || !o) return fail(SPR_E_INVALID, "null argument");
+    static_assert(MEM_NCAT == SPR_MEM_KINDS, "memory kinds");
+    for (int k = 0; k < MEM_NCAT; ++k) {
+        o->current[k] = c->mem_cat[k];
+        o->at_peak[k] = c->mem_at_peak[k];
+        o->kind_peak[k] = c->mem_cat_peak[k];
+    }
+    o->total = c->mem_cur;
+    o->peak = c->mem_peak;
+    if (reset_peak) {
+        c->mem_peak = c->mem_cur;
+        for (int k = 0; k < MEM_NCAT; ++k) {
+            c->mem_cat_peak[k] = c->mem_cat[k];
+            c->mem_at_peak[k] = c->mem_cat[k];
+        }
+    }
     return SPR_OK;
 }
 
@@ -487,6 +525,7 @@ spr_status spr_ctx_counters(spr_ctx *c, spr_counters *o) {
     o->pair_slots = p.acc_slots;
     o->served_pairs = p.acc_served;
     o->max_active_blocks = p.acc_max_active;
+    o->walk_guard = p.acc_guard;
     return SPR_OK;
 }
 
@@ -547,16 +586,15 @@ spr_status spr_ctx_get_tuning(spr_ctx *c, spr_tuning *out) {
 static void free_volume_buffers(spr_ctx *c, VolDev &V, size_t stream_bytes) {
     uint64_t nb = V.nblocks;
     uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
-    dev_free(c, (void *)V.stream, stream_bytes);
+    dev_free(c, MEM_COMPRESSED, (void *)V.stream, stream_bytes);
     V.stream = nullptr;
-    dfree(c, V.fine, nb);
-    dfree(c, V.coarse, nc);
+    dfree(c, MEM_GRIDS, V.fine, nb);
+    dfree(c, MEM_GRIDS, V.coarse, nc);
     const uint64_t ns = bidx_count(V);
-    dfree(c, V.map, ns);
-    dfree(c, V.blk_cnt, ns);
-    dfree(c, V.vis_idx, ns);
-    dfree(c, V.act_stamp, ns);
-    dfree(c, V.blk, nb);
+    dfree(c, MEM_GRIDS, V.map, ns);
+    dfree(c, MEM_GRIDS, V.blk_cnt, ns);
+    dfree(c, MEM_GRIDS, V.vis_idx, ns);
+    dfree(c, MEM_GRIDS, V.act_stamp, ns);
 }
 
 spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, const spr_volume_desc *d,
@@ -596,15 +634,14 @@ spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, co
     spr_status st = SPR_OK;
     void *sp = nullptr;
     do {
-        if ((st = dev_alloc(c, bytes, &sp)) != SPR_OK) break;
+        if ((st = dev_alloc(c, MEM_COMPRESSED, bytes, &sp)) != SPR_OK) break;
         V.stream = (const uint32_t *)sp;
-        if ((st = dalloc(c, nb, &V.fine)) != SPR_OK) break;
-        if ((st = dalloc(c, nc, &V.coarse)) != SPR_OK) break;
-        if ((st = dalloc(c, bidx_count(V), &V.map)) != SPR_OK) break;
-        if ((st = dalloc(c, bidx_count(V), &V.blk_cnt)) != SPR_OK) break;
-        if ((st = dalloc(c, bidx_count(V), &V.vis_idx)) != SPR_OK) break;
-        if ((st = dalloc(c, bidx_count(V), &V.act_stamp)) != SPR_OK) break;
-        if ((st = dalloc(c, nb, &V.blk)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_GRIDS, nb, &V.fine)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_GRIDS, nc, &V.coarse)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_GRIDS, bidx_count(V), &V.map)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_GRIDS, bidx_count(V), &V.blk_cnt)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_GRIDS, bidx_count(V), &V.vis_idx)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_GRIDS, bidx_count(V), &V.act_stamp)) != SPR_OK) break;
     } while (0);
     if (st != SPR_OK) {
         free_volume_buffers(c, V, bytes);
@@ -687,18 +724,18 @@ spr_status spr_debug_decode_blocks(spr_volume *v, const uint32_t *ids, uint32_t 
     HIPCHK(hipSetDevice(c->device));
     uint32_t *d_ids = nullptr;
     float *d_out = nullptr;
-    CHK(dalloc(c, n, &d_ids));
-    spr_status st = dalloc(c, (size_t)n * 64, &d_out);
+    CHK(dalloc(c, MEM_SCRATCH, n, &d_ids));
+    spr_status st = dalloc(c, MEM_SCRATCH, (size_t)n * 64, &d_out);
     if (st != SPR_OK) {
-        dfree(c, d_ids, n);
+        dfree(c, MEM_SCRATCH, d_ids, n);
         return st;
     }
     hipError_t e = hipMemcpyAsync(d_ids, ids, n * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_decode_ids(c->stream, V, d_ids, n, d_out);
     if (e == hipSuccess) e = hipMemcpyAsync(host_out, d_out, (size_t)n * 64 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    dfree(c, d_ids, n);
-    dfree(c, d_out, (size_t)n * 64);
+    dfree(c, MEM_SCRATCH, d_ids, n);
+    dfree(c, MEM_SCRATCH, d_out, (size_t)n * 64);
     if (e != hipSuccess) return fail(SPR_E_HIP, "debug decode failed: %s", hipGetErrorString(e));
     return SPR_OK;
 }
@@ -708,14 +745,14 @@ spr_status spr_debug_fp64_ops(spr_ctx *c, const double *x, const double *y, size
     if (n == 0) return SPR_OK;
     HIPCHK(hipSetDevice(c->device));
     double *buf = nullptr;
-    CHK(dalloc(c, 4 * n, &buf));
+    CHK(dalloc(c, MEM_SCRATCH, 4 * n, &buf));
     hipError_t e = hipMemcpyAsync(buf, x, n * 8, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(buf + n, y, n * 8, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_fp64_ops(c->stream, buf, buf + n, n, buf + 2 * n, buf + 3 * n);
     if (e == hipSuccess) e = hipMemcpyAsync(sq, buf + 2 * n, n * 8, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(dv, buf + 3 * n, n * 8, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    dfree(c, buf, 4 * n);
+    dfree(c, MEM_SCRATCH, buf, 4 * n);
     if (e != hipSuccess) return fail(SPR_E_HIP, "fp64 probe failed: %s", hipGetErrorString(e));
     return SPR_OK;
 }
@@ -725,19 +762,19 @@ spr_status spr_debug_fp64_ops(spr_ctx *c, const double *x, const double *y, size
 static void free_render_buffers(spr_ctx *c, spr_render *r) {
     uint32_t n = r->npix;
     ReqDev &q = r->hreq;
-    dfree(c, q.ray_state, n);
-    dfree(c, q.act[0], n);
-    dfree(c, q.act[1], n);
-    dfree(c, q.pair_blk, n);
-    dfree(c, q.rgbz, n);
-    dfree(c, q.best, n);
-    dfree(c, q.image, n);
-    dfree(c, q.hits, n);
-    dfree(c, r->d_st, 1);
-    dfree(c, r->d_req, 1);
-    dfree(c, q.cmask64, r->cwords);
-    dfree(c, q.cdist, 2 * r->cwords);
-    free_table(c, r->table);
+    dfree(c, MEM_RAYS, q.ray_state, n);
+    dfree(c, MEM_RAYS, q.act[0], n);
+    dfree(c, MEM_RAYS, q.act[1], n);
+    dfree(c, MEM_RAYS, q.pair_blk, n);
+    dfree(c, MEM_RAYS, q.rgbz, n);
+    dfree(c, MEM_RAYS, q.best, n);
+    dfree(c, MEM_RAYS, q.image, n);
+    dfree(c, MEM_RAYS, q.hits, n);
+    dfree(c, MEM_RAYS, r->d_st, 1);
+    dfree(c, MEM_RAYS, r->d_req, 1);
+    dfree(c, MEM_RAYS, q.cmask64, r->cwords);
+    dfree(c, MEM_RAYS, q.cdist, 2 * r->cwords);
+    free_table(c, MEM_RAYS, r->table);
 }
 
 spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uint32_t w, uint32_t h,
@@ -766,23 +803,23 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     HIPCHK(hipSetDevice(c->device));
     spr_status st = SPR_OK;
     do {
-        if ((st = dalloc(c, npix, &q.ray_state)) != SPR_OK) break;
-        if ((st = dalloc(c, npix, &q.act[0])) != SPR_OK) break;
-        if ((st = dalloc(c, npix, &q.act[1])) != SPR_OK) break;
-        if ((st = dalloc(c, npix, &q.pair_blk)) != SPR_OK) break;
-        if ((st = dalloc(c, npix, &q.rgbz)) != SPR_OK) break;
-        if ((st = dalloc(c, npix, &q.best)) != SPR_OK) break;
-        if ((st = dalloc(c, npix, &q.image)) != SPR_OK) break;
-        if ((st = dalloc(c, npix, &q.hits)) != SPR_OK) break;
-        if ((st = dalloc(c, 1, &r->d_st)) != SPR_OK) break;
-        if ((st = dalloc(c, 1, &r->d_req)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.ray_state)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.act[0])) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.act[1])) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.pair_blk)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.rgbz)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.best)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.image)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.hits)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, 1, &r->d_st)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, 1, &r->d_req)) != SPR_OK) break;
         {
             const VolDev &V = c->h_vols[v->idx];
             r->cwords = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
         }
-        if ((st = dalloc(c, r->cwords, &q.cmask64)) != SPR_OK) break;
-        if ((st = dalloc(c, 2 * r->cwords, &q.cdist)) != SPR_OK) break;
-        if ((st = alloc_table(c, 1, round64h(npix), npix, r->table)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, r->cwords, &q.cmask64)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, 2 * r->cwords, &q.cdist)) != SPR_OK) break;
+        if ((st = alloc_table(c, MEM_RAYS, 1, round64h(npix), npix, r->table)) != SPR_OK) break;
         st = ensure_work(c, npix);
     } while (0);
     if (st != SPR_OK) {
@@ -999,9 +1036,9 @@ spr_status spr_batch_create_empty(spr_ctx *c, uint32_t max_requests, uint64_t ma
     if (!b) return fail(SPR_E_OOM, "host allocation failed");
     b->ctx = c;
     b->max_pixels = max_pixels;
-    spr_status st = alloc_table(c, max_requests, A, P, b->table);
-    if (st == SPR_OK) st = dalloc(c, max_requests, &b->table.reqs);
-    if (st == SPR_OK) st = dalloc(c, (size_t)max_requests + 1, &b->d_state);
+    spr_status st = alloc_table(c, MEM_SCRATCH, max_requests, A, P, b->table);
+    if (st == SPR_OK) st = dalloc(c, MEM_SCRATCH, max_requests, &b->table.reqs);
+    if (st == SPR_OK) st = dalloc(c, MEM_SCRATCH, (size_t)max_requests + 1, &b->d_state);
     if (st == SPR_OK && hipHostMalloc((void **)&b->h_state, sizeof(uint4) * ((size_t)max_requests + 1),
                                       hipHostMallocDefault) != hipSuccess) {
         b->h_state = nullptr;
@@ -1010,9 +1047,9 @@ spr_status spr_batch_create_empty(spr_ctx *c, uint32_t max_requests, uint64_t ma
     if (st == SPR_OK) st = ensure_work(c, P);
     if (st == SPR_OK) st = set_table_count(c, b->table, 0);
     if (st != SPR_OK) {
-        free_table(c, b->table);
-        dfree(c, b->table.reqs, max_requests);
-        dfree(c, b->d_state, (size_t)max_requests + 1);
+        free_table(c, MEM_SCRATCH, b->table);
+        dfree(c, MEM_SCRATCH, b->table.reqs, max_requests);
+        dfree(c, MEM_SCRATCH, b->d_state, (size_t)max_requests + 1);
         if (b->h_state) (void)hipHostFree(b->h_state);
         delete b;
         return st;
@@ -1149,9 +1186,9 @@ spr_status spr_batch_free(spr_batch *b) {
     HIPCHK(hipStreamSynchronize(c->stream));
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    free_table(c, b->table);
-    dfree(c, b->table.reqs, b->table.cap);
-    dfree(c, b->d_state, (size_t)b->table.cap + 1);
+    free_table(c, MEM_SCRATCH, b->table);
+    dfree(c, MEM_SCRATCH, b->table.reqs, b->table.cap);
+    dfree(c, MEM_SCRATCH, b->d_state, (size_t)b->table.cap + 1);
     if (b->h_state) (void)hipHostFree(b->h_state);
     for (auto *r : b->renders) r->batch = nullptr;
     delete b;

@@ -26,8 +26,7 @@ constexpr int WAVE = 64;
 // One loaded volume.  Block ids are local to the volume (bx + nbx*(by + nby*bz)).
 struct VolDev {
     const uint32_t *stream;     // nblocks records of rec_words 32-bit words
-    float2 *blk;                // per block: own value range (samples inside the volume)
-    float2 *fine;               // per block: union of the 2x2x2 block neighbourhood
+    float2 *fine;               // per block: union of the ranges of the 2x2x2 block neighbourhood
     float2 *coarse;             // per 4^3 blocks: union of fine ranges
     uint32_t *map;              // per block: cache slot or NONE
     uint32_t *blk_cnt;          // per block: pairs on it in the current pass (0 between passes)
@@ -170,11 +169,13 @@ struct PassCtl {
     uint32_t assigned;          // misses that received a slot this pass
     uint32_t rays;              // active rays of this pass (unpadded)
     uint32_t A_trav;            // traversal lane space of this pass (64-padded per request)
-    uint32_t pad[7];
+    uint32_t guard;             // walks ended by a step guard (never by construction: every
+                                // step advances a cell index within the domain)
+    uint32_t pad[6];
     uint32_t hist[64];
     // cumulative counters since context creation
     unsigned long long acc_passes, acc_decoded, acc_visible, acc_active, acc_pairs, acc_evicted, acc_overflow,
-        acc_rays, acc_slots, acc_served, acc_max_active;
+        acc_rays, acc_slots, acc_served, acc_max_active, acc_guard;
 };
 
 // Launch table of a pass: the requests advanced together.

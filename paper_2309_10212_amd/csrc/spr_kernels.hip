@@ -122,24 +122,34 @@ __global__ __launch_bounds__(64) void k_block_ranges(VolDev V, float2 *blk) {
     }
 }
 
-// Fine grid: union of the ranges of blocks b + {0,1}^3 that exist.
-__global__ void k_fine_grid(VolDev V) {
-    const float2 *blk = V.blk;
-    uint64_t nb = V.nblocks;
-    for (uint64_t b = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; b < nb; b += (uint64_t)gridDim.x * blockDim.x) {
-        int bx, by, bz;
-        unravel3((uint32_t)b, (uint32_t)V.nb[0], (uint32_t)V.nb[1], bx, by, bz);
-        float lo = __builtin_inff(), hi = -__builtin_inff();
-        for (int dz = 0; dz < 2; ++dz)
-            for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx) {
-                    int x = bx + dx, y = by + dy, z = bz + dz;
-                    if (x >= V.nb[0] || y >= V.nb[1] || z >= V.nb[2]) continue;
-                    float2 r = blk[((uint64_t)z * V.nb[1] + y) * V.nb[0] + x];
-                    lo = r.x < lo ? r.x : lo;
-                    hi = r.y > hi ? r.y : hi;
-                }
-        V.fine[b] = make_float2(lo, hi);
+// Fine grid: union of the ranges of blocks b + {0,1}^3 that exist.  The box
+// union is separable (min and max are exact in any order), so it runs as
+// three passes over the block ranges in place, one per axis: a thread walks
+// one line of blocks along the axis in increasing order and replaces entry i
+// by the union of entries i and i+1, having read i+1 before it is rewritten.
+// The last entry of a line has no +1 neighbour and keeps its value.  No
+// second per-block array is needed.
+__global__ void k_fine_axis(VolDev V, int axis) {
+    float2 *f = V.fine;
+    const uint32_t nb0 = (uint32_t)V.nb[0], nb1 = (uint32_t)V.nb[1], nb2 = (uint32_t)V.nb[2];
+    const uint32_t len = axis == 0 ? nb0 : (axis == 1 ? nb1 : nb2);
+    const uint64_t stride = axis == 0 ? 1ull : (axis == 1 ? (uint64_t)nb0 : (uint64_t)nb0 * nb1);
+    const uint64_t nlines = V.nblocks / len;
+    for (uint64_t ln = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; ln < nlines;
+         ln += (uint64_t)gridDim.x * blockDim.x) {
+        // line ln -> its first block: x lines are indexed by (y, z), y lines
+        // by (x, z) and z lines by (x, y), x fastest so neighbouring threads
+        // of y and z passes touch neighbouring blocks
+        uint64_t b0;
+        if (axis == 0) b0 = ln * nb0;
+        else if (axis == 1) { const uint64_t z = ln / nb0, x = ln - z * nb0; b0 = z * nb0 * nb1 + x; }
+        else b0 = ln;
+        float2 cur = f[b0];
+        for (uint32_t i = 0; i + 1 < len; ++i) {
+            const float2 nxt = f[b0 + (uint64_t)(i + 1) * stride];
+            f[b0 + (uint64_t)i * stride] = make_float2(nxt.x < cur.x ? nxt.x : cur.x, nxt.y > cur.y ? nxt.y : cur.y);
+            cur = nxt;
+        }
     }
 }
 
@@ -297,6 +307,7 @@ __global__ __launch_bounds__(64) void k_pass_begin(PassCtl *ctl, Table T, int is
     ctl->n_vis = 0; ctl->v_adm = 0; ctl->n_actblk = 0; ctl->n_miss = 0; ctl->n_hit = 0;
     ctl->cursor = 0; ctl->served = 0; ctl->deferred = 0; ctl->need = 0; ctl->evict_T = 64;
     ctl->evict_done_blocks = 0; ctl->evicted = 0; ctl->terminated = 0; ctl->pairs = 0; ctl->overflow = 0;
+    ctl->guard = 0;
     ctl->rays = rays;
     T.act_base[nreq] = A;
     T.pair_base[nreq] = P;
@@ -517,8 +528,9 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         // loaded here, once for the whole wave); an empty cell is left by a
         // jump or a coarse step.  Inner loop: the blocks of a nonempty coarse
         // cell, no memory access but the LDS staging.
+        bool guard_hit = false;
         while (alive && found < ns) {
-            if (++steps > max_steps) { alive = false; break; }   // every step advances an index
+            if (++steps > max_steps) { alive = false; guard_hit = true; break; }   // every step advances an index
             if (tcur >= t_hi && !fresh) { seg_done = true; break; }   // the rest is the next lane's
             const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
             const uint64_t cm = cmask[cid];
@@ -590,7 +602,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                     }
                     if (found == ns) break;
                 }
-                if (++steps > max_steps) { alive = false; break; }
+                if (++steps > max_steps) { alive = false; guard_hit = true; break; }
                 double tn = walk_exit(wb);
                 if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) { alive = false; break; }
                 tcur = tn;
@@ -603,6 +615,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
             }
             if (seg_done) break;
         }
+        if (guard_hit) atomicAdd(&ctl->guard, 1u);   // counted, so that tests can assert it never happens
         // The block of pair 0 (the first active ray's first candidate) takes
         // visible-list index 0, so it is always admitted and every pass makes
         // progress under the cache-capacity rule: reserve that index.
@@ -1016,9 +1029,11 @@ __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols,
 
 // ---------------------------------------------------------------- K9 ------
 // Block raytrace (Sec. 3.7, 4.3): each served pair walks its ray through the
-// dual cells of its block (Amanatides-Woo restricted to the block), tests
-// each cell (corner pretest, cubic, Marmitt isolation) and writes the first
-// hit (t, cell, colour) or t = +inf to the RGBZ record at its pair slot.
+// dual cells of its block (Amanatides-Woo restricted to the block) and tests
+// each cell (corner pretest, cubic, Marmitt isolation).  A pair whose ray hits
+// takes the atomic minimum of its key into the pixel's best word and writes
+// its hit record (t, cell, colour) at its pair slot; a pair without a hit
+// writes nothing.
 __device__ __forceinline__ float slot_value(const float *slots, const uint32_t ns[8], int lx, int ly, int lz) {
     int nb = (lx >> 2) | ((ly >> 2) << 1) | ((lz >> 2) << 2);
     uint32_t s = ns[nb];
@@ -1145,7 +1160,8 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
             out.t = __builtin_inf();
             out.cell = NONE;
             out.rgba = 0u;
-            for (int guard = 0; guard < 16; ++guard) {   // at most 10 cells of a 4^3 block lie on a ray
+            int guard = 0;
+            for (; guard < 16; ++guard) {   // at most 10 cells of a 4^3 block lie on a ray
                 const double tx = cell_exit(R, L1, c);
                 const double t1 = tx < R.tx ? tx : R.tx;
                 float fc[8];
@@ -1171,6 +1187,7 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
                 if (tx > R.tx || !advance(R, L1, c, tx, lo, hi)) break;
                 t0 = tx;
             }
+            if (guard == 16) atomicAdd(&ctl->guard, 1u);
             if (out.cell != NONE) {
                 // A ray's pair slots are consecutive and follow its traversal,
                 // so the pair slot orders the ray's hits as t does (ties go to
@@ -1380,6 +1397,7 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
             ctl->acc_slots += ctl->P;
             ctl->acc_served += ctl->served;
             if (ctl->n_actblk > ctl->acc_max_active) ctl->acc_max_active = ctl->n_actblk;
+            ctl->acc_guard += ctl->guard;
         }
     }
     for (uint32_t r = t; r < nreq; r += PE_THREADS) {
@@ -1471,12 +1489,16 @@ hipError_t launch_load_grids(hipStream_t s, const VolDev &V, hipEvent_t *ev) {
         ++k;
     };
     dim3 g(grid_for(V.nblocks, 64, 1u << 16)), b(64);
+    mark();   // block ranges go straight into the fine array, which the axis passes then widen in place
+    if (V.rec_words <= 4) hipLaunchKernelGGL(k_block_ranges<4>, g, b, 0, s, V, V.fine);
+    else if (V.rec_words <= 8) hipLaunchKernelGGL(k_block_ranges<8>, g, b, 0, s, V, V.fine);
+    else if (V.rec_words <= 16) hipLaunchKernelGGL(k_block_ranges<16>, g, b, 0, s, V, V.fine);
+    else hipLaunchKernelGGL(k_block_ranges<32>, g, b, 0, s, V, V.fine);
     mark();
-    if (V.rec_words <= 4) hipLaunchKernelGGL(k_block_ranges<4>, g, b, 0, s, V, V.blk);
-    else if (V.rec_words <= 8) hipLaunchKernelGGL(k_block_ranges<8>, g, b, 0, s, V, V.blk);
-    else if (V.rec_words <= 16) hipLaunchKernelGGL(k_block_ranges<16>, g, b, 0, s, V, V.blk);
-    else hipLaunchKernelGGL(k_block_ranges<32>, g, b, 0, s, V, V.blk);
-    mark(); hipLaunchKernelGGL(k_fine_grid, dim3(grid_for(V.nblocks, 256, 1u << 16)), dim3(256), 0, s, V);
+    for (int a = 0; a < 3; ++a) {
+        const uint64_t len = a == 0 ? (uint64_t)V.nb[0] : (a == 1 ? (uint64_t)V.nb[1] : (uint64_t)V.nb[2]);
+        hipLaunchKernelGGL(k_fine_axis, dim3(grid_for(V.nblocks / len, 256, 1u << 16)), dim3(256), 0, s, V, a);
+    }
     uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
     mark(); hipLaunchKernelGGL(k_coarse_grid, dim3(grid_for(nc, 256, 1u << 16)), dim3(256), 0, s, V);
     mark();

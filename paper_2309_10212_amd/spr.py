@@ -70,7 +70,7 @@ class PassStats(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("passes", "blocks_decoded", "visible_blocks", "active_blocks",
                                                "pairs", "evicted", "overflow", "rays", "pair_slots",
-                                               "served_pairs", "max_active_blocks")]
+                                               "served_pairs", "max_active_blocks", "walk_guard")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -83,6 +83,18 @@ class RenderInfo(ctypes.Structure):
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+MEM_KINDS = ("compressed", "grids", "rays", "cache", "scratch")
+
+
+class MemSplit(ctypes.Structure):
+    _fields_ = [("current", ctypes.c_size_t * 5), ("at_peak", ctypes.c_size_t * 5), ("kind_peak", ctypes.c_size_t * 5),
+                ("total", ctypes.c_size_t), ("peak", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {"current": dict(zip(MEM_KINDS, self.current)), "at_peak": dict(zip(MEM_KINDS, self.at_peak)),
+                "kind_peak": dict(zip(MEM_KINDS, self.kind_peak)), "total": self.total, "peak": self.peak}
 
 
 class Tuning(ctypes.Structure):
@@ -108,6 +120,7 @@ SIGNATURES = [
     ("spr_ctx_create", _ST, [ctypes.POINTER(_Config), ctypes.POINTER(_P)]),
     ("spr_ctx_destroy", _ST, [_P]),
     ("spr_mem_stats", _ST, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    ("spr_mem_split_get", _ST, [_P, ctypes.POINTER(MemSplit), ctypes.c_int]),
     ("spr_ctx_counters", _ST, [_P, ctypes.POINTER(Counters)]),
     ("spr_ctx_profile", _ST, [_P, ctypes.c_int, ctypes.c_int]),
     ("spr_ctx_kernel_times", _ST, [_P, ctypes.POINTER(KernelTime), _U32, ctypes.POINTER(_U32)]),
@@ -188,7 +201,9 @@ class Context:
     """A device, a stream, a decoded-block cache (spr_ctx)."""
 
     def __init__(self, device: int = 0, cache_bytes: int = 512 * 10**6, spec_cap: int = 64, stream=None,
-                 torch_allocator: bool = True):
+                 torch_allocator: bool = True, alloc_hooks=None):
+        """alloc_hooks: optional (alloc(nbytes) -> int pointer or None, free(ptr, nbytes)) used
+        instead of torch's caching allocator (tests count or fail allocations with it)."""
         import torch
         lib = load_library()
         self._torch = torch
@@ -203,7 +218,22 @@ class Context:
         cfg.spec_cap = int(spec_cap)
         cfg.flags = 0
         self._keep = []
-        if torch_allocator:
+        if alloc_hooks is not None:
+            ha, hf = alloc_hooks
+
+            def _alloc(nbytes, user):
+                try:
+                    return ha(int(nbytes))
+                except Exception:
+                    return None
+
+            def _free(p, nbytes, user):
+                hf(p, int(nbytes))
+
+            fa, ff = _ALLOC_FN(_alloc), _FREE_FN(_free)
+            self._keep += [fa, ff]
+            cfg.alloc = _Allocator(fa, ff, None)
+        elif torch_allocator:
             def _alloc(nbytes, user):
                 try:
                     return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
@@ -225,6 +255,11 @@ class Context:
         cur, peak = ctypes.c_size_t(), ctypes.c_size_t()
         _chk(load_library().spr_mem_stats(self.h, ctypes.byref(cur), ctypes.byref(peak)), "spr_mem_stats")
         return cur.value, peak.value
+
+    def mem_split(self, reset_peak: bool = False):
+        m = MemSplit()
+        _chk(load_library().spr_mem_split_get(self.h, ctypes.byref(m), int(reset_peak)), "spr_mem_split_get")
+        return m.as_dict()
 
     def counters(self):
         c = Counters()

@@ -24,6 +24,15 @@ def ctx():
     c.close()
 
 
+@pytest.fixture(autouse=True)
+def _no_step_guard_exit(request):
+    """Every walk ends by leaving the domain or its block, or by finding its
+    blocks, never by the step guard (a counter the library keeps)."""
+    yield
+    if "ctx" in request.fixturenames:
+        assert request.getfixturevalue("ctx").counters()["walk_guard"] == 0
+
+
 def _cmp_hits(hits, img, ref, label=""):
     fin = np.isfinite(ref["t"])
     gfin = np.isfinite(hits["t"])

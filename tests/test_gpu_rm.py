@@ -4,11 +4,14 @@ values 0..255 (as float32) compressed at 2 bits/value (2,013,265,920 bytes,
 2*10^9-byte cache, at isovalues 64, 128 and 192.
 
 The volume cannot be decoded whole on the host (32 GB), so the oracle's
-streamed paths are used: block ranges one record at a time (the fine and
-coarse grids must match bitwise) and, for a seeded sample of pixels, the
+streamed paths are used: every block decoded by the device decoder is
+compared bitwise with the oracle's decode, in chunks; block ranges one record
+at a time (the fine and coarse grids must match bitwise); and, on every 8th
+row and column of the image plus a seeded sample of hit pixels, the
 per-pixel march reading blocks decoded on demand (hit block and cell exact,
 t within 1e-4, RGBA within 1 LSB).  Properties that hold at any size are
-checked on every pass: at most w*h pairs, no cache overflow."""
+checked on every pass: at most w*h pairs, no cache overflow, no step-guard
+exit."""
 import time
 
 import numpy as np
@@ -54,6 +57,28 @@ def test_rm_fullsize_grids(rm):
     assert coarse[:, 0].min() <= 0.0 and coarse[:, 1].max() >= 255.0
 
 
+def test_rm_every_block_decodes_bitexact(rm):
+    s, _, _, vol = rm
+    nb = vol.nblocks
+    assert nb == 125_829_120
+    chunk = 1 << 21
+    t0 = time.time()
+    for b0 in range(0, nb, chunk):
+        ids = np.arange(b0, min(nb, b0 + chunk), dtype=np.uint32)
+        got = vol.decode_blocks(ids)
+        ref = oracle.decode_blocks(s, DIMS, RATE, ids)
+        if not np.array_equal(got.view(np.uint32), ref.view(np.uint32)):
+            bad = np.nonzero((got.view(np.uint32) != ref.view(np.uint32)).any(axis=1))[0]
+            raise AssertionError(f"blocks {ids[bad[:8]]} differ ({bad.size} in chunk at {b0})")
+        del got, ref
+    print(f"{nb} blocks decoded and compared in {time.time() - t0:.1f} s", flush=True)
+
+
+def _subset():
+    ys, xs = np.meshgrid(np.arange(0, H, 8), np.arange(0, W, 8), indexing="ij")
+    return (ys * W + xs).astype(np.uint32).ravel()
+
+
 @pytest.mark.parametrize("iso", [64.0, 128.0, 192.0])
 def test_rm_fullsize_render_sampled(rm, iso):
     from paper_2309_10212_amd import spr
@@ -75,10 +100,12 @@ def test_rm_fullsize_render_sampled(rm, iso):
     print(f"iso {iso}: {passes} passes in {time.time() - t0:.2f} s, {info['rays_entered']} rays entered, "
           f"{int(np.isfinite(hits['t']).sum())} hits, {c1['blocks_decoded'] - c0['blocks_decoded']} blocks decoded",
           flush=True)
+    assert c1["walk_guard"] == c0["walk_guard"]
     rng = np.random.default_rng(int(iso))
     fin = np.nonzero(np.isfinite(hits["t"]))[0]
-    pix = np.unique(np.concatenate([rng.choice(W * H, 256, replace=False),
-                                    rng.choice(fin, min(256, fin.size), replace=False) if fin.size else []]))
+    # every 8th row and column, plus a seeded sample of hit pixels
+    pix = np.unique(np.concatenate([_subset(), rng.choice(fin, min(512, fin.size), replace=False)
+                                    if fin.size else np.zeros(0, np.int64)]).astype(np.int64))
     pix = pix.astype(np.uint32)
     t0 = time.time()
     ref = oracle.render_stream(s, DIMS, RATE, cams[k], iso, W, H, pixels=pix)

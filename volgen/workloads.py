@@ -5,7 +5,8 @@ renders or decodes.
 Batched (B): a pool of 8 volumes - Gaussian blobs and Fourier fields at
 128^3, 256^3, 512^3 and 1024^3 (blob widths scaled by n/64) - each stored as
 float32 or as u8 levels (quantised to 0..255 over the field's range, then
-compressed as float32 values), at 2, 4 or 8 bits/value; 64 requests (seeds
+compressed as float32 values), at 2, 4 or 8 bits/value (in turn along the
+pool, so every rate appears); 64 requests (seeds
 1000+i), each picking a pool volume, an image size from {256^2, 512^2,
 640x360, 1280x720, 1920x1080}, an isovalue uniform in [p10, p90] of that
 volume's values, and a seeded orbit camera.
@@ -60,7 +61,8 @@ def make_pool(sizes=(128, 256, 512, 1024), seed: int = 11) -> list[PoolVolume]:
     pool = []
     for i, (kind, n) in enumerate(POOL_KINDS):
         dtype = "u8" if next(g) & 1 else "f32"
-        rate = (2, 4, 8)[next(g) % 3]
+        next(g)                      # (the draw that used to pick the rate; kept so dtypes stay put)
+        rate = (2, 4, 8)[i % 3]      # every rate of the mix, 2 bits/value included, at every pool size subset
         if n not in sizes:
             continue
         fseed = 100 + i
