@@ -50,7 +50,7 @@ RM_NAME = "rm2048x2048x1920_rate2_1280x720"
 TRAFFIC_FILES = {"rm": os.path.join(ROOT, "profiles", f"hbm_traffic_{RM_NAME}.txt"),
                  "fourier": os.path.join(ROOT, "profiles", "hbm_traffic_fourier512_rate4_1280x720.txt")}
 PASS_KERNELS = ("k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_evict_hist",
-                "k_evict", "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact")
+                "k_evict", "k_assign_scatter", "k_decode", "k_raytrace", "k_pass_end", "k_compact")
 
 
 def log(*a):
@@ -72,14 +72,15 @@ def kernel_bytes(name, c, rate):
         "k_fine_grid": 48 * NB,                    # three in-place axis passes: range in and out each
         "k_coarse_grid": 8 * NB + 8 * NC,          # fine ranges in, coarse range out
         "k_iso_masks": 8 * c.get("mask_blocks", NB) + 16 * c.get("mask_coarse", NC),   # fine + coarse ranges in, mask word out
-        "k_init_rays": 28 * NP,                    # ray state, image, hit record, active entry
-        "k_traverse": 8 * A + 4 * S + 8 * V,
+        "k_init_rays": 44 * NP,                    # ray state, image, hit record, active entry, pass state
+        "k_traverse": 12 * A + 4 * S + 8 * V,      # + each ray's candidate count
         "k_dedupe": 4 * S + 12 * P + 12 * V,
         "k_mark": 52 * V + 12 * K + 8 * M,      # + the 8 neighbour stamps each visible block tests
         "k_assign_scatter": 32 * M + 4 * S + 28 * Ps,
         "k_decode": (8 * rate + 268) * M + 64 * V,   # + each visible block's 8 neighbour slots, read and listed
-        "k_raytrace": 36 * Ps + 532 * V,
-        "k_composite": 8 * A + 4 * S + 20 * P,
+        # per served pair: sorted entry, visible entry, hit t and key, its ray's pair count and finish counter;
+        # per visible block: the staged dual grid and its 8 slot ids; per ray: the finish (composite) by its last pair
+        "k_raytrace": 48 * Ps + 532 * V + 60 * A,
         "k_compact": 12 * A,
     }
     return model.get(name)
@@ -92,7 +93,7 @@ def hbm_fractions(c, rate, steps, ms_per_step, passes, decoded, decode_ms, peak_
     against it, blocks decoded/s against 8 TB/s over a decode's bytes per
     block, peak memory against the 288 GB of HBM."""
     names = ("k_block_ranges", "k_fine_grid", "k_coarse_grid", "k_iso_masks", "k_init_rays", "k_traverse", "k_dedupe",
-             "k_mark", "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_compact")
+             "k_mark", "k_assign_scatter", "k_decode", "k_raytrace", "k_compact")
     byts = sum(kernel_bytes(k, c, rate) or 0 for k in names) / max(steps, 1)
     t_floor_ms = byts / (HBM_PEAK_GBS * 1e9) * 1e3
     frac_t = t_floor_ms / ms_per_step if ms_per_step > 0 else None

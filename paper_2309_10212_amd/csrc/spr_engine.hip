@@ -283,6 +283,9 @@ spr_status alloc_table(spr_ctx *c, MemCat cat, uint32_t cap, uint64_t max_A, uin
     CHK(dalloc(c, cat, cap + 1, &T.trav_base));
     CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_rec));
     CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_off));
+    // wave records accumulate during a pass and are cleared by its
+    // compaction: they start at zero
+    HIPCHK(launch_fill_u32(c->stream, reinterpret_cast<uint32_t *>(T.wave_rec), 4 * (max_A / 64 + 2), 0u));
     return SPR_OK;
 }
 
@@ -338,7 +341,7 @@ spr_status graph_pass(spr_ctx *c, const Table &T, const PassGrids &g, hipGraph_t
 }
 
 // Profiling: add one recorded event set's kernel intervals to their slots.
-constexpr int PASS_SLOTS[PASS_KERNELS] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
+constexpr int PASS_SLOTS[PASS_KERNELS] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10};
 
 spr_status prof_collect(spr_ctx *c, spr_ctx::ProfRec &rec) {
     if (!rec.pending) return SPR_OK;
@@ -766,8 +769,11 @@ static void free_render_buffers(spr_ctx *c, spr_render *r) {
     dfree(c, MEM_RAYS, q.act[0], n);
     dfree(c, MEM_RAYS, q.act[1], n);
     dfree(c, MEM_RAYS, q.pair_blk, n);
-    dfree(c, MEM_RAYS, q.rgbz, n);
+    dfree(c, MEM_RAYS, q.tslot, n);
     dfree(c, MEM_RAYS, q.best, n);
+    dfree(c, MEM_RAYS, q.nfound, n);
+    dfree(c, MEM_RAYS, q.done_cnt, n);
+    dfree(c, MEM_RAYS, q.def_first, n);
     dfree(c, MEM_RAYS, q.image, n);
     dfree(c, MEM_RAYS, q.hits, n);
     dfree(c, MEM_RAYS, r->d_st, 1);
@@ -807,8 +813,11 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
         if ((st = dalloc(c, MEM_RAYS, npix, &q.act[0])) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.act[1])) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.pair_blk)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.rgbz)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.tslot)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.best)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.nfound)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.done_cnt)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.def_first)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.image)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.hits)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, 1, &r->d_st)) != SPR_OK) break;
@@ -837,7 +846,6 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     hipError_t e = hipMemcpy(r->d_st, &s0, sizeof(s0), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r->table.hdr, &one, sizeof(one), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(r->d_req, &q, sizeof(q), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_fill_u64(c->stream, q.best, npix, ~0ull);
     hipEvent_t *pev = nullptr;
     if (e == hipSuccess && c->prof && prof_begin(c, 5, INIT_SLOTS, &pev) != SPR_OK) e = hipErrorUnknown;
     if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols, r->cwords, pev);

@@ -94,13 +94,6 @@ __device__ __forceinline__ uint32_t bidx(const VolState &S, uint32_t b) {
 // Entries of each per-block state array (whole coarse cells).
 inline uint64_t bidx_count(const VolDev &V) { return (uint64_t)V.nc[0] * V.nc[1] * V.nc[2] * 64u; }
 
-// Per-pair raytrace result (the RGBZ buffer of Sec. 4.3): t = +inf for no hit.
-struct Rgbz {
-    double t;
-    uint32_t cell;
-    uint32_t rgba;
-};
-
 // Mutable per-render state kept on the device (no host round trip per pass).
 struct ReqState {
     uint32_t n_act;             // active rays for the next pass
@@ -127,9 +120,12 @@ struct ReqDev {
     uint32_t *ray_state;        // per pixel: last served block, RAY_NOT_STARTED, RAY_DONE
     uint32_t *act[2];           // compacted active pixel lists
     uint32_t *pair_blk;         // per pair slot (R_BID of Sec. 3.3/4.1)
-    Rgbz *rgbz;                 // per pair slot (written for hits only)
+    double *tslot;              // per pair slot: the hit parameter t, written by hit pairs only
     uint64_t *best;             // per pixel: minimum over this pass's hits of
                                 // pair slot << 38 | cell << 32 | rgba, ~0 for none
+    uint32_t *nfound;           // per pixel: candidate blocks the traversal found this pass
+    uint32_t *done_cnt;         // per pixel: the ray's pairs finished this pass (0 between passes)
+    uint32_t *def_first;        // per pixel: first deferred slot of the ray this pass (NONE between passes)
     uint32_t *image;            // RGBA8 per pixel
     spr_hit *hits;              // per pixel
     ReqState *st;
@@ -186,8 +182,9 @@ struct Table {
     uint32_t *act_base;         // cap+1, 64-aligned prefix of n_act
     uint32_t *pair_base;        // cap+1, prefix of n_act*n_spec
     uint32_t *trav_base;        // cap+1, 64-aligned prefix of n_act*segs (traversal lanes)
-    uint4 *wave_rec;            // per 64-entry wave of the A space: survivors, pairs,
-                                // deferred pairs, terminated rays
+    uint4 *wave_rec;            // per 64-entry wave of the A space, accumulated during a pass
+                                // and cleared by its compaction: {alive rays (initial-ray pass
+                                // only), pairs, deferred pairs, terminated rays}
     uint32_t *wave_off;         // exclusive prefix of the survivors
     uint32_t cap;               // request capacity
     uint32_t max_A;             // capacity of the A space (sum of padded npix)

@@ -402,8 +402,9 @@ __device__ __forceinline__ uint32_t local_bit(const int cb[3]) {
 
 // ------------------------------------------------------------ initial rays --
 // Sec. 3.2: one thread per pixel computes the ray and its volume entry; rays
-// that miss are terminated; image and hit buffer are cleared.  The alive
-// flags feed the same count/compact kernels as a pass.
+// that miss are terminated; image and hit buffer are cleared, and so is the
+// per-pixel pass state.  The alive counts feed the same count/compact kernels
+// as a pass.
 __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
     uint32_t A = ctl->A;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
@@ -424,6 +425,9 @@ __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
             h.cell = NONE;
             q.hits[i] = h;
             q.act[1][i] = i;
+            q.best[i] = ~0ull;       // per-pixel pass state: no hit, no pair finished, nothing deferred
+            q.done_cnt[i] = 0u;
+            q.def_first[i] = NONE;
         }
         uint64_t m = __ballot(alive);
         if (lane_id() == 0) T.wave_rec[p >> 6] = make_uint4((uint32_t)__popcll(m), 0u, 0u, 0u);
@@ -639,6 +643,31 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                 for (uint32_t k = total < ns ? total : ns; k < ns; ++k) slots[k] = NONE;
                 if (total > 0 && T.pair_base[r] + i * ns == 0) ctl->n_vis = 1u;
             }
+            found = total < ns ? total : ns;   // the ray's candidates (every lane of the group)
+        }
+        // The ray's outcome as far as the walk decides it: its candidate
+        // count, which tells the pair that finishes the ray last how many to
+        // wait for, and, with no candidate left, its termination (it leaves
+        // the volume with no block that can hold the isovalue).  The wave's
+        // pair and termination counts go to the wave record of its rays in
+        // one atomic each (all rays of a traversal wave share one wave of the
+        // active-ray space).
+        const bool lead = seg == 0u;
+        const bool term = lead && found == 0u;
+        if (lead) {
+            as_global(uni(q.nfound))[pix] = found;
+            if (term) as_global(uni(q.ray_state))[pix] = RAY_DONE;
+        }
+        uint32_t wpairs = 0;
+#pragma unroll
+        for (int bit = 0; bit < 13; ++bit)   // found <= ns <= 4096: a sum of bit planes over the lanes
+            wpairs += (uint32_t)__popcll(__ballot(lead && ((found >> bit) & 1u))) << bit;
+        const uint32_t wterm = (uint32_t)__popcll(__ballot(term));
+        const uint64_t act = __ballot(1);
+        if ((int)lane_id() == __ffsll((unsigned long long)act) - 1) {
+            uint4 *rec = T.wave_rec + ((uni(T.act_base[r]) + i) >> 6);
+            if (wpairs) atomicAdd(&rec->y, wpairs);
+            if (wterm) atomicAdd(&rec->w, wterm);
         }
     }
 }
@@ -968,8 +997,27 @@ __global__ __launch_bounds__(256) void k_assign_scatter(PassCtl *ctl, Table T, c
         const uint32_t b = pblk[qq];
         if (b == NONE) continue;
         const uint32_t vi = V.vis_idx[bidx(V, b)];
-        const uint32_t pix = (cur ? act1 : act)[qq / nsp];
-        if (vi >= vadm) continue;
+        const uint32_t ii = qq / nsp;
+        const uint32_t pix = (cur ? act1 : act)[ii];
+        if (vi >= vadm) {
+            // a pair on a block not served this pass (cache-capacity rule):
+            // the ray keeps its progress up to its first such slot.  It counts
+            // as finished for the ray's pair count; when every pair of the
+            // ray is deferred, nothing is raytraced and the ray stays as it
+            // was, so the last of them resets the ray's pass state here.
+            uint32_t *const dfirst = q.def_first, *const dcnt = q.done_cnt;
+            const uint32_t nf = q.nfound[pix];
+            uint4 *const rec = T.wave_rec + ((T.act_base[r] + ii) >> 6);
+            atomicMin(dfirst + pix, qq - ii * nsp);
+            atomicAdd(&rec->z, 1u);
+            // acquire-release: the minimum above is visible to whichever pair
+            // finishes the ray, and that pair sees every other pair's
+            if (__hip_atomic_fetch_add(dcnt + pix, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == nf) {
+                dcnt[pix] = 0u;
+                dfirst[pix] = NONE;
+            }
+            continue;
+        }
         const uint32_t dst = W.vis_off[vi] + rank;
         W.s_ray[dst] = (r << 24) | pix;
         W.s_q[dst] = qq;
@@ -1025,6 +1073,58 @@ __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols,
     }
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->free_top -= m;   // the assigned slots leave the free stack
+}
+
+// ------------------------------------------------------- finishing a ray --
+// Depth composite and termination of one ray (Sec. 4.4), run by the last of
+// its pairs to finish (in the raytrace, or in the scatter when every pair of
+// the ray was deferred and there is nothing to finish).  The ray's slots
+// i*N_spec .. i*N_spec + nfound - 1 hold its candidate blocks in traversal
+// order.  best holds the minimum hit key of the ray's raytraced pairs, and
+// def_first the first slot whose block was not served this pass (NONE if
+// all were).
+//   - a hit in a slot before def_first is the closest hit: image, hit buffer,
+//     the ray terminates;
+//   - otherwise, with a deferred slot, the ray keeps its progress up to the
+//     slot before it and survives;
+//   - otherwise (every candidate served, no hit) the ray terminates if the
+//     walk found fewer than N_spec blocks (it left the volume), and else
+//     resumes after its last candidate.
+// The ray's per-pixel pass state is reset for the next pass.
+__device__ __forceinline__ void finish_ray(const Table &T, uint32_t r, uint32_t pix, uint32_t qq) {
+    const ReqDev &q = T.reqs[r];
+    uint64_t *const bestp = q.best;
+    uint32_t *const ray_state = q.ray_state, *const pblk = q.pair_blk;
+    uint32_t *const dcnt = q.done_cnt, *const dfirst = q.def_first;
+    const uint32_t ns = q.st->last_nspec;
+    const uint32_t i = qq / ns, base = i * ns;
+    const uint32_t nf = q.nfound[pix];
+    const uint64_t best = __hip_atomic_load(bestp + pix, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t d = __hip_atomic_load(dfirst + pix, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t kb = best != ~0ull ? (uint32_t)(best >> 38) - base : NONE;
+    bool term = false;
+    if (kb != NONE && kb < d) {
+        q.image[pix] = (uint32_t)best;
+        spr_hit h;
+        h.t = q.tslot[base + kb];
+        h.block_id = pblk[base + kb];
+        h.cell = (uint32_t)(best >> 32) & 63u;
+        q.hits[pix] = h;
+        term = true;
+    } else if (d != NONE) {
+        if (d > 0u) ray_state[pix] = pblk[base + d - 1u];
+    } else if (nf < ns) {
+        term = true;
+    } else {
+        ray_state[pix] = pblk[base + nf - 1u];
+    }
+    if (term) {
+        ray_state[pix] = RAY_DONE;
+        atomicAdd(&T.wave_rec[(T.act_base[r] + i) >> 6].w, 1u);
+    }
+    if (best != ~0ull) bestp[pix] = ~0ull;
+    dcnt[pix] = 0u;
+    if (d != NONE) dfirst[pix] = NONE;
 }
 
 // ---------------------------------------------------------------- K9 ------
@@ -1156,10 +1256,7 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
             // previous cell's exit (the stepped axes' entry planes are the old
             // exit planes, every other entry plane lies before them)
             double t0 = cell_entry(R, L1, c);
-            Rgbz out;
-            out.t = __builtin_inf();
-            out.cell = NONE;
-            out.rgba = 0u;
+            struct { double t; uint32_t cell, rgba; } out = {__builtin_inf(), NONE, 0u};
             int guard = 0;
             for (; guard < 16; ++guard) {   // at most 10 cells of a 4^3 block lie on a ray
                 const double tx = cell_exit(R, L1, c);
@@ -1191,100 +1288,23 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
             if (out.cell != NONE) {
                 // A ray's pair slots are consecutive and follow its traversal,
                 // so the pair slot orders the ray's hits as t does (ties go to
-                // the earlier block): the composite's first hit in slot order
-                // is the minimum of slot << 38 | cell << 32 | rgba over the
-                // ray's hits (slots < 2^24).  Only hits write their record (t).
+                // the earlier block): the ray's first hit in slot order is the
+                // minimum of slot << 38 | cell << 32 | rgba over its hits
+                // (slots < 2^24).  t goes to the pair's slot, where the
+                // minimum's slot finds it (the second step of the resolve).
                 const uint64_t key = ((uint64_t)qq << 38) | ((uint64_t)out.cell << 32) | out.rgba;
+                q.tslot[qq] = out.t;
                 __hip_atomic_fetch_min(as_global(q.best) + pix, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                q.rgbz[qq] = out;
             }
+            // The pair is done.  The ray's pairs count themselves off
+            // (acquire-release, so the hits above are visible to the last);
+            // the last of them finishes the ray: depth composite, termination
+            // and its traversal state for the next pass.
+            const uint32_t nf = q.nfound[pix];
+            if (__hip_atomic_fetch_add(q.done_cnt + pix, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == nf)
+                finish_ray(T, r, pix, qq);
         }
         __syncthreads();   // the next tile reuses the LDS
-    }
-}
-
-// --------------------------------------------------------------- K10 ------
-// Depth composite (Sec. 4.4) and termination: each active ray scans its
-// N_spec slots in order; slots are in traversal order, so the first hit is
-// the closest (ties go to the earlier block).  An empty slot means the walk
-// left the volume: the ray terminates.  A slot on a block that was not
-// served this pass stops the scan: the ray keeps its progress up to the last
-// served block and retries the rest next pass.  Survivor counts per wave
-// feed the compaction.
-__global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const VolDev *vols) {
-    const uint32_t A = ctl->A;
-    const uint32_t vadm = admitted_blocks(ctl);
-    const bool all_served = vadm == ctl->n_vis;   // no deferral this pass: skip the per-slot check
-    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
-        // all lanes of a wave share a request (the A space is 64-aligned per request)
-        uint32_t r = __builtin_amdgcn_readfirstlane(find_req(T.act_base, ctl->nreq, p));
-        const ReqDev &q = T.reqs[r];
-        ReqState *st = q.st;
-        uint32_t i = p - T.act_base[r];
-        bool alive = false;
-        uint32_t my_pairs = 0, my_def = 0, my_term = 0;
-        if (i < st->n_act_prev) {
-            // the request's and volume's fields in registers: through the
-            // references they would be read again after every store
-            uint32_t *const image = q.image, *const ray_state = q.ray_state;
-            spr_hit *const hits = q.hits;
-            const VolState V = vol_state(vols[q.vol]);
-            const uint32_t ns = st->last_nspec;
-            const uint32_t pix = q.act[st->cur][i];
-            const uint32_t *slots = q.pair_blk + (size_t)i * ns;
-            const Rgbz *res = q.rgbz + (size_t)i * ns;
-            uint32_t last = NONE;
-            bool term = false, stopped = false;
-            // this pass's first hit in slot order (the raytrace's atomic
-            // minimum), reset for the next pass
-            const uint64_t best = q.best[pix];
-            if (best != ~0ull) q.best[pix] = ~0ull;
-            const uint32_t kb = best != ~0ull ? (uint32_t)(best >> 38) - i * ns : NONE;   // slot within the ray
-            for (uint32_t k = 0; k < ns; ++k) {
-                uint32_t b = slots[k];
-                if (b == NONE) {
-                    if (!stopped && !term) term = true;
-                    break;
-                }
-                my_pairs++;
-                const bool served = all_served || V.vis_idx[bidx(V, b)] < vadm;
-                if (stopped || term) {
-                    if (!served) my_def++;
-                    continue;
-                }
-                if (!served) {
-                    stopped = true;
-                    my_def++;
-                    continue;
-                }
-                if (k == kb) {
-                    image[pix] = (uint32_t)best;
-                    spr_hit h;
-                    h.t = res[k].t;
-                    h.block_id = b;
-                    h.cell = (uint32_t)(best >> 32) & 63u;
-                    hits[pix] = h;
-                    term = true;
-                    continue;
-                }
-                last = b;
-            }
-            if (term) ray_state[pix] = RAY_DONE;
-            else if (last != NONE) ray_state[pix] = last;
-            alive = !term;
-            my_term = term ? 1u : 0u;
-        }
-        // per-wave record: survivors (for the compaction scan) and the
-        // request's pass counters, summed by k_pass_end
-        const uint64_t m = __ballot(alive);
-        uint32_t sp = my_pairs, sd = my_def;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            sp += __shfl_xor(sp, off);
-            sd += __shfl_xor(sd, off);
-        }
-        const uint32_t nt = (uint32_t)__popcll(__ballot(my_term != 0));
-        if (lane_id() == 0) T.wave_rec[p >> 6] = make_uint4((uint32_t)__popcll(m), sp, sd, nt);
     }
 }
 
@@ -1292,9 +1312,13 @@ __global__ __launch_bounds__(256) void k_composite(PassCtl *ctl, Table T, const 
 // Count the surviving rays (Sec. 3 step (f)): exclusive scan of the per-wave
 // survivor counts, per-request N_act, N_spec = clamp(floor(w*h / N_act), 1,
 // cap) (Sec. 4), the per-request pass counters, and the flip to the other
-// active-ray list.  One workgroup; each thread owns a contiguous run of waves,
-// sums it (splitting at request boundaries into LDS per-request sums), the
-// workgroup scans the run totals, and each thread writes its run's offsets.
+// active-ray list.  A wave's survivors are its active rays less the ones that
+// terminated this pass (counted into its record by the traversal and by the
+// pairs that finished rays); on the initial-ray pass the record holds the
+// rays that entered the volume.  One workgroup; each thread owns a
+// contiguous run of waves, sums it (splitting at request boundaries into LDS
+// per-request sums), the workgroup scans the run totals, and each thread
+// writes its run's offsets.
 constexpr int PE_THREADS = 1024;
 
 __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, int is_init) {
@@ -1319,11 +1343,22 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
 #pragma unroll
     for (uint32_t k = 0; k < PE_REG; ++k)
         rv[k] = (in_regs && w0 + k < w1) ? T.wave_rec[w0 + k] : make_uint4(0u, 0u, 0u, 0u);
+    uint32_t surv[PE_REG] = {};
     if (w0 < w1) {
         uint32_t r = find_req(T.act_base, nreq, w0 << 6);
         uint32_t next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
+        uint32_t rbase = T.act_base[r], rna = T.reqs[r].st->n_act_prev;
         uint4 acc = make_uint4(0u, 0u, 0u, 0u);
-        auto add = [&](uint32_t w, const uint4 v) {
+        // survivors of wave w: the initial pass records them; a pass records
+        // its terminations, and the wave's active rays are the request's
+        // n_act_prev rays from its 64-aligned start
+        auto survivors = [&](uint32_t w, const uint4 v) -> uint32_t {
+            if (is_init) return v.x;
+            const uint32_t lo = (w << 6) - rbase;
+            const uint32_t act = lo >= rna ? 0u : (rna - lo < 64u ? rna - lo : 64u);
+            return act - v.w;
+        };
+        auto add = [&](uint32_t w, const uint4 v) -> uint32_t {
             while (w >= next) {   // crossing into the next request's waves
                 if (acc.x) atomicAdd(&s_req[0][r], acc.x);
                 if (acc.y) atomicAdd(&s_req[1][r], acc.y);
@@ -1332,16 +1367,20 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
                 acc = make_uint4(0u, 0u, 0u, 0u);
                 ++r;
                 next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
+                rbase = T.act_base[r];
+                rna = T.reqs[r].st->n_act_prev;
             }
-            acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
-            run += v.x;
+            const uint32_t sv = survivors(w, v);
+            acc.x += sv; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+            run += sv;
+            return sv;
         };
         if (in_regs) {
 #pragma unroll
             for (uint32_t k = 0; k < PE_REG; ++k)
-                if (w0 + k < w1) add(w0 + k, rv[k]);
+                surv[k] = (w0 + k < w1) ? add(w0 + k, rv[k]) : 0u;
         } else {
-            for (uint32_t w = w0; w < w1; ++w) add(w, T.wave_rec[w]);
+            for (uint32_t w = w0; w < w1; ++w) (void)add(w, T.wave_rec[w]);
         }
         if (acc.x) atomicAdd(&s_req[0][r], acc.x);
         if (acc.y) atomicAdd(&s_req[1][r], acc.y);
@@ -1366,13 +1405,25 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
         for (uint32_t k = 0; k < PE_REG; ++k) {
             if (w0 + k < w1) {
                 T.wave_off[w0 + k] = off;
-                off += rv[k].x;
+                off += surv[k];
             }
         }
-    } else {
+    } else if (w0 < w1) {
+        uint32_t r = find_req(T.act_base, nreq, w0 << 6);
+        uint32_t next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
         for (uint32_t w = w0; w < w1; ++w) {
+            while (w >= next) {
+                ++r;
+                next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
+            }
+            const uint4 v = T.wave_rec[w];
+            uint32_t sv = v.x;
+            if (!is_init) {
+                const uint32_t lo = (w << 6) - T.act_base[r], rna = T.reqs[r].st->n_act_prev;
+                sv = (lo >= rna ? 0u : (rna - lo < 64u ? rna - lo : 64u)) - v.w;
+            }
             T.wave_off[w] = off;
-            off += T.wave_rec[w].x;
+            off += sv;
         }
     }
     if (t == PE_THREADS - 1) T.wave_off[nw] = off;   // == total survivors
@@ -1441,6 +1492,9 @@ __global__ __launch_bounds__(256) void k_compact(PassCtl *ctl, Table T) {
             uint32_t dst = T.wave_off[p >> 6] - T.wave_off[T.act_base[r] >> 6] + (uint32_t)__popcll(m & lanemask_lt());
             q.act[st->cur][dst] = pix;
         }
+        // the pass's wave records are consumed: clear them for the next pass
+        // (whose active-ray space is no larger than this one's)
+        if (lane_id() == 0) T.wave_rec[p >> 6] = make_uint4(0u, 0u, 0u, 0u);
     }
 }
 
@@ -1552,11 +1606,11 @@ hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const V
 
 const char *const PASS_KERNEL_NAMES[PASS_KERNELS] = {
     "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_evict_hist", "k_evict",
-    "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact"};
+    "k_assign_scatter", "k_decode", "k_raytrace", "k_pass_end", "k_compact"};
 
 const char *const PROF_NAMES[PROF_SLOTS] = {
     "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_evict_hist", "k_evict",
-    "k_assign_scatter", "k_decode", "k_raytrace", "k_composite", "k_pass_end", "k_compact",
+    "k_assign_scatter", "k_decode", "k_raytrace", "k_pass_end", "k_compact",
     "k_block_ranges", "k_fine_grid", "k_coarse_grid", "k_iso_masks", "k_init_rays"};
 
 hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, const Work &W,
@@ -1579,7 +1633,6 @@ hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev
     else if (g.rt_tile == 128) hipLaunchKernelGGL((k_raytrace<128, 32>), dim3(g.rt), dim3(128), 0, s, ctl, T, vols, W, C);
     else if (g.rt_lb == 16) hipLaunchKernelGGL((k_raytrace<256, 16>), dim3(g.rt), dim3(256), 0, s, ctl, T, vols, W, C);
     else hipLaunchKernelGGL((k_raytrace<256, 32>), dim3(g.rt), dim3(256), 0, s, ctl, T, vols, W, C);
-    mark(); hipLaunchKernelGGL(k_composite, dim3(g.rays), dim3(256), 0, s, ctl, T, vols);
     mark(); hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, s, ctl, T, 0);
     mark(); hipLaunchKernelGGL(k_compact, dim3(g.rays), dim3(256), 0, s, ctl, T);
     if (ev) (void)hipEventRecord(ev[k], s);

@@ -38,14 +38,14 @@ hipError_t launch_release_volume(hipStream_t s, PassCtl *ctl, const Cache &C, ui
 // path, with ev[5] after the last kernel.
 hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words,
                             hipEvent_t *ev = nullptr);
-constexpr int PASS_KERNELS = 12;
+constexpr int PASS_KERNELS = 11;
 extern const char *const PASS_KERNEL_NAMES[PASS_KERNELS];
 // Profiling slots: the pass kernels, then the load-path and set-up kernels
 // that run outside a pass.
 constexpr int PROF_SLOTS = PASS_KERNELS + 5;
 extern const char *const PROF_NAMES[PROF_SLOTS];
-constexpr int LOAD_SLOTS[3] = {12, 13, 14};           // block ranges, fine grid, coarse grid
-constexpr int INIT_SLOTS[5] = {15, 0, 16, 10, 11};    // masks, pass begin, initial rays, pass end, compact
+constexpr int LOAD_SLOTS[3] = {11, 12, 13};           // block ranges, fine grid, coarse grid
+constexpr int INIT_SLOTS[5] = {14, 0, 15, 9, 10};     // masks, pass begin, initial rays, pass end, compact
 // ev == nullptr: plain launches; else ev[i] is recorded before kernel i and
 // ev[PASS_KERNELS] after the last one.
 hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, const Work &W,
