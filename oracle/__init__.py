@@ -63,6 +63,21 @@ def _load():
         lib.orc_schedule_lists.argtypes = [ctypes.c_uint64, ctypes.c_size_t, P, P, P, P, ctypes.c_long,
                                            ctypes.c_long, ctypes.c_long, ctypes.c_uint32, ctypes.c_long, P]
         lib.orc_schedule_lists.restype = ctypes.c_long
+        lib.orc_schedule_policy.argtypes = [P, i, i, i, ctypes.POINTER(_Cam), ctypes.c_float, i, i,
+                                            ctypes.c_uint32, ctypes.c_uint32, ctypes.c_long, P]
+        lib.orc_schedule_policy.restype = ctypes.c_long
+        lib.orc_schedule_lists_policy.argtypes = [ctypes.c_uint64, ctypes.c_size_t, P, P, P, P, P, P, ctypes.c_long,
+                                                  ctypes.c_long, ctypes.c_long, ctypes.c_uint32, ctypes.c_uint32,
+                                                  ctypes.c_long, P]
+        lib.orc_schedule_lists_policy.restype = ctypes.c_long
+        lib.orc_pixel_candidates.argtypes = [P, i, i, i, ctypes.POINTER(_Cam), ctypes.c_float, i, i, i, i, P, P,
+                                             ctypes.c_long, P, P]
+        lib.orc_pixel_candidates.restype = ctypes.c_long
+        lib.orc_ray_weight.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.orc_ray_weight.restype = ctypes.c_uint32
+        lib.orc_nspec_ray.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                      ctypes.c_uint32]
+        lib.orc_nspec_ray.restype = ctypes.c_uint32
         lib.orc_render_stream.argtypes = [P, ctypes.c_size_t, i, i, i, i, ctypes.POINTER(_Cam), ctypes.c_float,
                                           i, i, P, ctypes.c_size_t, P, P, P, P, P]
         lib.orc_block_ranges_stream.argtypes = [P, ctypes.c_size_t, i, i, i, i, P]
@@ -245,28 +260,59 @@ def nspec(slots: int, n_act: int, cap: int = 64) -> int:
     return int(_load().orc_nspec(slots, n_act, cap))
 
 
-SCHED_FIELDS = ("n_active", "n_spec", "pairs", "visible", "active_blocks", "terminated")
+SCHED_FIELDS = ("n_active", "n_spec", "pairs", "visible", "active_blocks", "terminated", "slots", "wsum")
+POLICY_UNIFORM, POLICY_PER_RAY = 0, 1
 
 
-def schedule(vol: np.ndarray, cam, iso: float, w: int, h: int, spec_cap: int, max_pass: int = 100000):
-    """Per-pass counters of the progressive speculative passes (Sec. 3, Sec. 4)."""
+def ray_weight(t: float, t_exit: float) -> int:
+    """Weight of a ray whose remaining walk starts at t (per-ray speculation)."""
+    return int(_load().orc_ray_weight(ctypes.c_double(t), ctypes.c_double(t_exit)))
+
+
+def pixel_candidates(vol: np.ndarray, cam, iso: float, w: int, h: int, px: int, py: int, cap: int = 1 << 16):
+    """(candidate blocks, weight after each, weight before the first, first-hit index) of one pixel."""
+    nx, ny, nz = _dims(vol)
+    v = np.ascontiguousarray(vol, np.float32)
+    lst = np.zeros(cap, np.uint32)
+    wl = np.zeros(cap, np.uint32)
+    hit = np.zeros(1, np.int64)
+    w0 = np.zeros(1, np.uint32)
+    cc = _cam(cam)
+    n = _load().orc_pixel_candidates(_p(v), nx, ny, nz, ctypes.byref(cc), ctypes.c_float(iso), w, h, px, py,
+                                     _p(lst), _p(wl), cap, _p(hit), _p(w0))
+    if n < 0:
+        raise RuntimeError(f"oracle.pixel_candidates failed with status {n}")
+    return lst[:n].copy(), wl[:n].copy(), int(w0[0]), int(hit[0])
+
+
+def nspec_ray(slots: int, n_act: int, wsum: int, w: int, cap: int = 64) -> int:
+    """Per-ray count min(cap, 1 + floor((slots - n_act) * w / wsum))."""
+    return int(_load().orc_nspec_ray(slots, n_act, wsum, w, cap))
+
+
+def schedule(vol: np.ndarray, cam, iso: float, w: int, h: int, spec_cap: int, max_pass: int = 100000,
+             policy: int = POLICY_UNIFORM):
+    """Per-pass counters of the progressive speculative passes (Sec. 3, Sec. 4;
+    policy 1: per-ray speculation counts)."""
     nx, ny, nz = _dims(vol)
     v = np.ascontiguousarray(vol, np.float32)
     st = np.zeros((max_pass, 8), np.uint64)
     cc = _cam(cam)
-    n = _load().orc_schedule(_p(v), nx, ny, nz, ctypes.byref(cc), ctypes.c_float(iso), w, h, spec_cap,
-                             max_pass, _p(st))
+    n = _load().orc_schedule_policy(_p(v), nx, ny, nz, ctypes.byref(cc), ctypes.c_float(iso), w, h, spec_cap,
+                                    policy, max_pass, _p(st))
     if n < 0:
         raise RuntimeError(f"oracle.schedule failed with status {n}")
-    return [dict(zip(SCHED_FIELDS, (int(x) for x in row[:6]))) for row in st[:n]]
+    return [dict(zip(SCHED_FIELDS, (int(x) for x in row))) for row in st[:n]]
 
 
 def schedule_lists(slots: int, lists, hit_idx, entered, nb_dims, spec_cap: int,
-                   max_pass: int = 100000):
+                   max_pass: int = 100000, policy: int = POLICY_UNIFORM, w0=None, wk=None):
     """Pass schedule (Sec. 3, Sec. 4) from explicit per-ray candidate-block lists.
 
     lists[i]: ordered candidate block ids of ray i; hit_idx[i]: index in it of
-    the block holding the first hit, or -1; entered[i]: ray entered the volume."""
+    the block holding the first hit, or -1; entered[i]: ray entered the volume.
+    policy 1 (per-ray counts) takes each ray's weight before its first
+    candidate (w0[i]) and after each candidate k (wk[i][k])."""
     n = len(lists)
     off = np.zeros(n + 1, np.uint64)
     for i, l in enumerate(lists):
@@ -277,11 +323,18 @@ def schedule_lists(slots: int, lists, hit_idx, entered, nb_dims, spec_cap: int,
     ent = np.ascontiguousarray(entered, np.uint8)
     st = np.zeros((max_pass, 8), np.uint64)
     nbx, nby, nbz = nb_dims
-    r = _load().orc_schedule_lists(slots, n, _p(off), _p(flat), _p(hit), _p(ent), nbx, nby, nbz, spec_cap,
-                                   max_pass, _p(st))
+    if policy == POLICY_PER_RAY:
+        w0a = np.ascontiguousarray(w0, np.uint32)
+        wka = np.ascontiguousarray(np.concatenate([np.asarray(x, np.uint32) for x in wk])
+                                   if n and off[-1] else np.zeros(1, np.uint32), np.uint32)
+        pw0, pwk = _p(w0a), _p(wka)
+    else:
+        pw0 = pwk = None
+    r = _load().orc_schedule_lists_policy(slots, n, _p(off), _p(flat), _p(hit), _p(ent), pw0, pwk, nbx, nby, nbz,
+                                          spec_cap, policy, max_pass, _p(st))
     if r < 0:
         raise RuntimeError(f"oracle.schedule_lists failed with status {r}")
-    return [dict(zip(SCHED_FIELDS, (int(x) for x in row[:6]))) for row in st[:r]]
+    return [dict(zip(SCHED_FIELDS, (int(x) for x in row))) for row in st[:r]]
 
 
 def blocks_containing(fine: np.ndarray, iso: float) -> int:

@@ -770,17 +770,60 @@ uint32_t orc_nspec(uint64_t slots, uint64_t n_act, uint32_t cap) {
     return (uint32_t)s;
 }
 
+/* Per-ray speculation counts (the per-ray count that the paper's conclusion
+ * names as future work, in place of Sec. 4's single count for all rays).
+ * This build's reading: a ray's weight is its remaining path in block
+ * lengths, w = 1 + floor((t_exit - t) / 4) (w = 1 once t >= t_exit), where t
+ * is where its remaining walk starts: the volume entry for a ray not yet
+ * started, else the parameter where it leaves its last served block.  With
+ * B = w*h slots, N active rays and W the sum of their weights, ray i gets
+ * n_i = min(cap, 1 + floor((B - N) * w_i / W)).  Every ray gets at least one
+ * slot, the counts sum to at most B, and equal weights give floor(B / N),
+ * Sec. 4's count. */
+uint32_t orc_ray_weight(double t, double t_exit) {
+    if (!(t < t_exit)) return 1u;
+    return 1u + (uint32_t)floor((t_exit - t) * 0.25);
+}
+
+uint32_t orc_nspec_ray(uint64_t slots, uint64_t n_act, uint64_t wsum, uint32_t w, uint32_t cap) {
+    if (n_act == 0 || wsum == 0) return 0;
+    uint64_t extra = slots > n_act ? ((slots - n_act) * (uint64_t)w) / wsum : 0;
+    uint64_t s = 1 + extra;
+    if (s > cap) s = cap;
+    return (uint32_t)s;
+}
+
+/* Parameter where the ray leaves block (bx,by,bz): the nearest of its exit
+ * planes at block level, where block plane m sits at sample 4m except the
+ * last one of an axis, which is the domain face n-1. */
+static double block_exit_tau(const ray_t *ray, long bx, long by, long bz) {
+    const long b[3] = {bx, by, bz};
+    double tn = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        long nplanes = (ray->n[a] - 1 + 3) / 4;   /* blocks that own dual cells on this axis */
+        long m;
+        if (ray->d[a] > 0) m = b[a] + 1;
+        else if (ray->d[a] < 0) m = b[a];
+        else continue;
+        long pos = m >= nplanes ? ray->n[a] - 1 : 4 * m;
+        double x = tau(ray, a, pos);
+        if (x < tn) tn = x;
+    }
+    return tn;
+}
+
 /* Candidate blocks of one ray: the distinct blocks of its dual-cell walk, in
  * walk order, whose fine range contains iso (Sec. 3.3: blocks whose combined
  * range does not contain the isovalue are skipped).  hit_idx = position of the
  * block holding the first hit cell, or -1. */
 static long ray_candidates(const float *vol, const float *fine, int nx, int ny, int nz, const cam_basis *cb,
-                           float iso, int px, int py, uint32_t **list, long *cap, long *hit_idx,
-                           int *entered) {
+                           float iso, int px, int py, uint32_t **list, uint32_t **wlist, long *cap, long *hit_idx,
+                           int *entered, uint32_t *w0) {
     ray_t ray;
     make_ray(cb, nx, ny, nz, px, py, &ray);
     *hit_idx = -1;
     *entered = ray.hit_volume;
+    *w0 = ray.hit_volume ? orc_ray_weight(ray.t_enter, ray.t_exit) : 0u;
     if (!ray.hit_volume) return 0;
     long nbx = nblk_axis(nx), nby = nblk_axis(ny);
     long c[3];
@@ -796,7 +839,10 @@ static long ray_candidates(const float *vol, const float *fine, int nx, int ny, 
                 if (n == *cap) {
                     *cap = *cap ? 2 * *cap : 64;
                     *list = (uint32_t *)realloc(*list, sizeof(uint32_t) * (size_t)*cap);
+                    *wlist = (uint32_t *)realloc(*wlist, sizeof(uint32_t) * (size_t)*cap);
                 }
+                /* the weight of a ray that resumes after this block */
+                (*wlist)[n] = orc_ray_weight(block_exit_tau(&ray, c[0] >> 2, c[1] >> 2, c[2] >> 2), ray.t_exit);
                 (*list)[n++] = b;
             }
         }
@@ -818,17 +864,24 @@ static long ray_candidates(const float *vol, const float *fine, int nx, int ny, 
  * from each ray's ordered candidate-block list.  slots = w*h (the virtual GPU
  * of Sec. 4).  Ray i's list is lists[off[i] .. off[i+1]); hit[i] is the index
  * in it of the block holding the first hit (or -1); entered[i] says whether the
- * ray entered the volume.  Each pass: N_spec from the active-ray count; every
- * active ray takes its next N_spec candidates; it terminates if its hit block
- * is among them or if it got fewer than N_spec blocks (it left the volume).
- * Per pass p: stats[8*p ..] = {n_active, n_spec, pairs, visible blocks,
- * active blocks (visible plus existing +x/+y/+z face, edge and corner
- * neighbours in the nbx*nby*nbz block grid), rays terminated, 0, 0}.
+ * ray entered the volume.  Each pass: every active ray gets a speculation
+ * count, takes its next that many candidates, and terminates if its hit block
+ * is among them or if it got fewer than its count (it left the volume).
+ * policy 0: one count for all rays, N_spec from the active-ray count (Sec. 4).
+ * policy 1: per-ray counts (orc_nspec_ray) from weights: w0[i] before the
+ * ray's first candidate, wk[off[i] + k] once it has been served candidate k
+ * (w0 and wk may be NULL for policy 0).
+ * Per pass p: stats[8*p ..] = {n_active, n_spec (the largest count), pairs,
+ * visible blocks, active blocks (visible plus existing +x/+y/+z face, edge
+ * and corner neighbours in the nbx*nby*nbz block grid), rays terminated,
+ * slots (the sum of the counts), weight sum}.
  * Returns the number of passes (<= max_pass) or a negative status. */
-long orc_schedule_lists(uint64_t slots, size_t nray, const uint64_t *off, const uint32_t *lists,
-                        const int64_t *hit, const uint8_t *entered, long nbx, long nby, long nbz,
-                        uint32_t spec_cap, long max_pass, uint64_t *stats) {
+long orc_schedule_lists_policy(uint64_t slots, size_t nray, const uint64_t *off, const uint32_t *lists,
+                               const int64_t *hit, const uint8_t *entered, const uint32_t *w0, const uint32_t *wk,
+                               long nbx, long nby, long nbz, uint32_t spec_cap, uint32_t policy, long max_pass,
+                               uint64_t *stats) {
     if (!off || !hit || !entered || !stats || spec_cap < 1 || nbx < 1 || nby < 1 || nbz < 1) return ORC_EINVAL;
+    if (policy > 1 || (policy == 1 && (!w0 || !wk))) return ORC_EINVAL;
     size_t nb = (size_t)nbx * nby * nbz;
     for (size_t i = 0; i < nray; ++i)
         for (uint64_t k = off[i]; k < off[i + 1]; ++k)
@@ -846,13 +899,25 @@ long orc_schedule_lists(uint64_t slots, size_t nray, const uint64_t *off, const 
     long p = 0;
     while (n_act > 0 && p < max_pass) {
         uint32_t ns = orc_nspec(slots, n_act, spec_cap);
-        uint64_t pairs = 0, vis = 0, actb = 0, term = 0, surv = 0;
+        uint64_t wsum = 0;
+        if (policy == 1)
+            for (size_t i = 0; i < nray; ++i)
+                if (act[i]) wsum += pos[i] == 0 ? w0[i] : wk[off[i] + (uint64_t)(pos[i] - 1)];
+        uint64_t pairs = 0, vis = 0, actb = 0, term = 0, surv = 0, nslots = 0;
+        uint32_t nmax = 0;
         uint32_t stamp = (uint32_t)(p + 1);
         for (size_t i = 0; i < nray; ++i) {
             if (!act[i]) continue;
+            uint32_t ni = ns;
+            if (policy == 1) {
+                uint32_t w = pos[i] == 0 ? w0[i] : wk[off[i] + (uint64_t)(pos[i] - 1)];
+                ni = orc_nspec_ray(slots, n_act, wsum, w, spec_cap);
+            }
+            nslots += ni;
+            if (ni > nmax) nmax = ni;
             int64_t len = (int64_t)(off[i + 1] - off[i]);
             int64_t take = len - pos[i];
-            if (take > (int64_t)ns) take = ns;
+            if (take > (int64_t)ni) take = ni;
             for (int64_t k = 0; k < take; ++k) {
                 uint32_t b = lists[off[i] + (uint64_t)(pos[i] + k)];
                 pairs++;
@@ -870,13 +935,14 @@ long orc_schedule_lists(uint64_t slots, size_t nray, const uint64_t *off, const 
                             }
                 }
             }
-            int done = (hit[i] >= pos[i] && hit[i] < pos[i] + take) || take < (int64_t)ns;
+            int done = (hit[i] >= pos[i] && hit[i] < pos[i] + take) || take < (int64_t)ni;
             pos[i] += take;
             if (done) { act[i] = 0; term++; }
             else surv++;
         }
         uint64_t *st = stats + 8 * p;
-        st[0] = n_act; st[1] = ns; st[2] = pairs; st[3] = vis; st[4] = actb; st[5] = term; st[6] = 0; st[7] = 0;
+        st[0] = n_act; st[1] = nmax; st[2] = pairs; st[3] = vis; st[4] = actb; st[5] = term; st[6] = nslots;
+        st[7] = wsum;
         n_act = surv;
         ++p;
     }
@@ -884,10 +950,41 @@ long orc_schedule_lists(uint64_t slots, size_t nray, const uint64_t *off, const 
     return p;
 }
 
-/* Candidate lists of every pixel of a render, then the pass schedule. */
-long orc_schedule(const float *vol, int nx, int ny, int nz, const orc_camera *cam, float iso, int w, int h,
-                  uint32_t spec_cap, long max_pass, uint64_t *stats) {
-    if (!vol || !cam || !stats || spec_cap < 1) return ORC_EINVAL;
+long orc_schedule_lists(uint64_t slots, size_t nray, const uint64_t *off, const uint32_t *lists,
+                        const int64_t *hit, const uint8_t *entered, long nbx, long nby, long nbz,
+                        uint32_t spec_cap, long max_pass, uint64_t *stats) {
+    return orc_schedule_lists_policy(slots, nray, off, lists, hit, entered, NULL, NULL, nbx, nby, nbz, spec_cap, 0,
+                                     max_pass, stats);
+}
+
+/* One pixel's candidate blocks (in walk order), the weight of the ray after
+ * each (wlist) and before the first (*w0), and the index of the block that
+ * holds its first hit (*hit_idx, -1 if none).  Returns the number of
+ * candidates (at most cap are stored) or a negative status. */
+long orc_pixel_candidates(const float *vol, int nx, int ny, int nz, const orc_camera *cam, float iso, int w, int h,
+                          int px, int py, uint32_t *list, uint32_t *wlist, long cap, int64_t *hit_idx, uint32_t *w0) {
+    if (!vol || !cam || !list || !wlist || !hit_idx || !w0) return ORC_EINVAL;
+    cam_basis cb;
+    if (make_basis(cam, w, h, &cb)) return ORC_EINVAL;
+    long nb = nblk_axis(nx) * nblk_axis(ny) * nblk_axis(nz);
+    float *fine = (float *)malloc(sizeof(float) * 2 * (size_t)nb);
+    if (!fine) return ORC_ENOMEM;
+    orc_grids(vol, nx, ny, nz, NULL, fine, NULL);
+    uint32_t *l = NULL, *wl = NULL;
+    long lcap = 0, hi;
+    int entered;
+    long n = ray_candidates(vol, fine, nx, ny, nz, &cb, iso, px, py, &l, &wl, &lcap, &hi, &entered, w0);
+    for (long k = 0; k < n && k < cap; ++k) { list[k] = l[k]; wlist[k] = wl[k]; }
+    *hit_idx = hi;
+    free(l); free(wl); free(fine);
+    return n;
+}
+
+/* Candidate lists of every pixel of a render, then the pass schedule under
+ * the given speculation policy (0: Sec. 4's single count, 1: per-ray counts). */
+long orc_schedule_policy(const float *vol, int nx, int ny, int nz, const orc_camera *cam, float iso, int w, int h,
+                         uint32_t spec_cap, uint32_t policy, long max_pass, uint64_t *stats) {
+    if (!vol || !cam || !stats || spec_cap < 1 || policy > 1) return ORC_EINVAL;
     cam_basis cb;
     if (make_basis(cam, w, h, &cb)) return ORC_EINVAL;
     long nbx = nblk_axis(nx), nby = nblk_axis(ny), nbz = nblk_axis(nz);
@@ -897,34 +994,46 @@ long orc_schedule(const float *vol, int nx, int ny, int nz, const orc_camera *ca
     orc_grids(vol, nx, ny, nz, NULL, fine, NULL);
     size_t npx = (size_t)w * h;
     uint32_t **lists = (uint32_t **)calloc(npx, sizeof(uint32_t *));
+    uint32_t **wl = (uint32_t **)calloc(npx, sizeof(uint32_t *));
     long *len = (long *)calloc(npx, sizeof(long));
     int64_t *hit = (int64_t *)calloc(npx, sizeof(int64_t));
     uint8_t *ent = (uint8_t *)calloc(npx, 1);
+    uint32_t *w0 = (uint32_t *)calloc(npx ? npx : 1, sizeof(uint32_t));
     uint64_t *off = (uint64_t *)calloc(npx + 1, sizeof(uint64_t));
-    if (!lists || !len || !hit || !ent || !off) {
-        free(fine); free(lists); free(len); free(hit); free(ent); free(off);
+    if (!lists || !wl || !len || !hit || !ent || !w0 || !off) {
+        free(fine); free(lists); free(wl); free(len); free(hit); free(ent); free(w0); free(off);
         return ORC_ENOMEM;
     }
 #pragma omp parallel for schedule(dynamic, 64)
     for (long i = 0; i < (long)npx; ++i) {
         long cap = 0, hi;
         int entered;
-        len[i] = ray_candidates(vol, fine, nx, ny, nz, &cb, iso, (int)(i % w), (int)(i / w), &lists[i], &cap,
-                                &hi, &entered);
+        len[i] = ray_candidates(vol, fine, nx, ny, nz, &cb, iso, (int)(i % w), (int)(i / w), &lists[i], &wl[i],
+                                &cap, &hi, &entered, &w0[i]);
         hit[i] = hi;
         ent[i] = (uint8_t)entered;
     }
     for (size_t i = 0; i < npx; ++i) off[i + 1] = off[i] + (uint64_t)len[i];
     uint32_t *flat = (uint32_t *)malloc(sizeof(uint32_t) * (off[npx] ? off[npx] : 1));
+    uint32_t *wflat = (uint32_t *)malloc(sizeof(uint32_t) * (off[npx] ? off[npx] : 1));
     long rc = ORC_ENOMEM;
-    if (flat) {
+    if (flat && wflat) {
         for (size_t i = 0; i < npx; ++i)
-            if (len[i]) memcpy(flat + off[i], lists[i], sizeof(uint32_t) * (size_t)len[i]);
-        rc = orc_schedule_lists(npx, npx, off, flat, hit, ent, nbx, nby, nbz, spec_cap, max_pass, stats);
+            if (len[i]) {
+                memcpy(flat + off[i], lists[i], sizeof(uint32_t) * (size_t)len[i]);
+                memcpy(wflat + off[i], wl[i], sizeof(uint32_t) * (size_t)len[i]);
+            }
+        rc = orc_schedule_lists_policy(npx, npx, off, flat, hit, ent, w0, wflat, nbx, nby, nbz, spec_cap, policy,
+                                       max_pass, stats);
     }
-    for (size_t i = 0; i < npx; ++i) free(lists[i]);
-    free(flat); free(fine); free(lists); free(len); free(hit); free(ent); free(off);
+    for (size_t i = 0; i < npx; ++i) { free(lists[i]); free(wl[i]); }
+    free(flat); free(wflat); free(fine); free(lists); free(wl); free(len); free(hit); free(ent); free(w0); free(off);
     return rc;
+}
+
+long orc_schedule(const float *vol, int nx, int ny, int nz, const orc_camera *cam, float iso, int w, int h,
+                  uint32_t spec_cap, long max_pass, uint64_t *stats) {
+    return orc_schedule_policy(vol, nx, ny, nz, cam, iso, w, h, spec_cap, 0, max_pass, stats);
 }
 
 /* Blocks whose fine range contains iso: what an extraction method that
