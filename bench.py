@@ -395,6 +395,34 @@ def run_rm(args):
     log(f"[bench] plain: {steps} requests, {value / 1e6:.1f} M rays/s, {el * 1e3 / steps:.3f} ms per request, "
         f"{passes / steps:.2f} passes")
 
+    # the same requests with per-ray speculation counts (plain path, the same
+    # cache state): the policy changes passes and work, never the image
+    per_ray = None
+    if not args.no_per_ray:
+        fresh_volume()
+        for cam, iso, _ in warm:
+            _request(spr, vol, cam, iso, w, h, cap)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pinfos = []
+        for cam, iso, _ in reqs:
+            r = spr.Render(vol, cam, iso, w, h, spec_cap=cap, policy=spr.SPEC_PER_RAY)
+            r.run()
+            pinfos.append(r.info())
+            r.free()
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t0
+        prays = sum(i["rays_entered"] for i in pinfos)
+        ppass = sum(i["passes"] for i in pinfos)
+        assert prays == rays, (prays, rays)
+        per_ray = {"rays_per_s": round(prays / pel, 1), "ms_per_step": round(pel * 1e3 / steps, 4),
+                   "passes_per_step": ppass / steps, "ms_per_pass": round(pel * 1e3 / max(ppass, 1), 4),
+                   "pairs_per_step": round(sum(i["pairs"] for i in pinfos) / steps, 1),
+                   "uniform_pairs_per_step": round(sum(i["pairs"] for i in infos) / steps, 1),
+                   "vs_uniform": round((prays / pel) / value, 3),
+                   "rule": "n_i = min(64, 1 + floor((w*h - N_act) w_i / W)), w_i = 1 + floor(remaining path / 4)"}
+        log(f"[bench] per-ray speculation: {per_ray}")
+
     # the same requests as one batch: one replayed pass advances all of them;
     # the clock starts before the first render set-up, as for the plain path
     batched = None
@@ -492,6 +520,7 @@ def run_rm(args):
                                          mem_steps["peak"]),
            "batched": batched,
            "batched_mix": mix,
+           "per_ray_speculation": per_ray,
            "bcmc_proxy": {"blocks_per_request": round(bcmc, 1),
                           "decoded_blocks_per_request": round(dc["blocks_decoded"] / steps, 1),
                           "decoded_ratio": round(bcmc * steps / max(dc["blocks_decoded"], 1), 2),
@@ -759,6 +788,7 @@ def main():
     ap.add_argument("--sweep", default="1,2,4,8,16", help="fourier: speculation caps for the sweep ('' = none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mix", action="store_true", help="rm: skip the 64-request mixed batched-vs-plain leg")
+    ap.add_argument("--no-per-ray", action="store_true", help="rm: skip the per-ray speculation leg")
     ap.add_argument("--cpu-views", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="bound on the oracle's timed work (the sample stops after the request that crosses it)")

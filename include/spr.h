@@ -115,7 +115,8 @@ typedef struct {
     uint32_t blocks_decoded;  /* cache misses decompressed this pass */
     uint32_t deferred_pairs;  /* pairs postponed because the cache was too small */
     uint32_t terminated;      /* rays that terminated this pass */
-    uint32_t reserved;
+    uint32_t slots;           /* pair slots the pass handed out: n_active * n_spec, or the sum of the
+                                 per-ray counts (SPR_SPEC_PER_RAY) */
     double utilization;       /* pairs / (w*h) */
     float ms;                 /* device time of the pass (HIP events) */
     float pad;
@@ -257,6 +258,19 @@ spr_status spr_render_begin(spr_volume *vol, const spr_camera *cam, float isoval
 /* Speculation cap of this render (Sec. 4 caps N_spec at 64); 1 disables
  * speculation.  Only before the first pass.  SPR_E_STATE afterwards. */
 spr_status spr_render_set_spec_cap(spr_render *r, uint32_t cap);
+/* Speculation policy of this render, only before the first pass
+ * (SPR_E_STATE afterwards).  SPR_SPEC_UNIFORM (the default): one count for
+ * every ray, N_spec = clamp(floor(w*h / N_act), 1, cap) (Sec. 4).
+ * SPR_SPEC_PER_RAY: a count per ray, the per-ray speculation count that the
+ * paper's conclusion leaves as future work; this library's rule gives ray i
+ * n_i = min(cap, 1 + floor((w*h - N_act) * w_i / W)), where w_i =
+ * 1 + floor((t_exit - t_i) / 4) is its remaining path in block lengths from
+ * where its remaining walk starts (t_i) and W the sum over the active rays, so
+ * every ray gets at least one slot and all of them at most w*h.  The image
+ * does not depend on the policy; the passes and their work do. */
+#define SPR_SPEC_UNIFORM 0u
+#define SPR_SPEC_PER_RAY 1u
+spr_status spr_render_set_spec_policy(spr_render *r, uint32_t policy);
 /* Enqueue one pass (Sec. 3 (a)-(f), Sec. 4): speculative traversal, mark
  * visible/active blocks, LRU cache update and decompression of misses, build
  * the per-block ray lists, raytrace visible blocks, depth composite, count

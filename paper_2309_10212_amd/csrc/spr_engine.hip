@@ -46,6 +46,7 @@ spr_status fail(spr_status st, const char *fmt, ...) {
 
 uint32_t round64h(uint64_t x) { return (uint32_t)((x + 63u) & ~63ull); }
 
+
 // What a device allocation holds (spr_mem_split reports bytes per kind).
 enum MemCat {
     MEM_COMPRESSED = 0,   // compressed streams
@@ -283,9 +284,11 @@ spr_status alloc_table(spr_ctx *c, MemCat cat, uint32_t cap, uint64_t max_A, uin
     CHK(dalloc(c, cat, cap + 1, &T.trav_base));
     CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_rec));
     CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_off));
-    // wave records accumulate during a pass and are cleared by its
-    // compaction: they start at zero
+    CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_w));
+    // wave records and weights accumulate during a pass and are cleared by
+    // its compaction: they start at zero
     HIPCHK(launch_fill_u32(c->stream, reinterpret_cast<uint32_t *>(T.wave_rec), 4 * (max_A / 64 + 2), 0u));
+    HIPCHK(launch_fill_u32(c->stream, T.wave_w, max_A / 64 + 2, 0u));
     return SPR_OK;
 }
 
@@ -296,6 +299,7 @@ void free_table(spr_ctx *c, MemCat cat, Table &T) {
     dfree(c, cat, T.trav_base, T.cap + 1);
     dfree(c, cat, T.wave_rec, T.max_A / 64 + 2);
     dfree(c, cat, T.wave_off, T.max_A / 64 + 2);
+    dfree(c, cat, T.wave_w, T.max_A / 64 + 2);
 }
 
 spr_status set_table_count(spr_ctx *c, Table &T, uint32_t n) {
@@ -774,6 +778,10 @@ static void free_render_buffers(spr_ctx *c, spr_render *r) {
     dfree(c, MEM_RAYS, q.nfound, n);
     dfree(c, MEM_RAYS, q.done_cnt, n);
     dfree(c, MEM_RAYS, q.def_first, n);
+    dfree(c, MEM_RAYS, q.rbase, n);
+    dfree(c, MEM_RAYS, q.rns, n);
+    dfree(c, MEM_RAYS, q.rw, n);
+    dfree(c, MEM_RAYS, q.pair_ray, n);
     dfree(c, MEM_RAYS, q.image, n);
     dfree(c, MEM_RAYS, q.hits, n);
     dfree(c, MEM_RAYS, r->d_st, 1);
@@ -818,6 +826,10 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
         if ((st = dalloc(c, MEM_RAYS, npix, &q.nfound)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.done_cnt)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.def_first)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.rbase)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.rns)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.rw)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_RAYS, npix, &q.pair_ray)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.image)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.hits)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, 1, &r->d_st)) != SPR_OK) break;
@@ -881,6 +893,20 @@ spr_status spr_render_set_spec_cap(spr_render *r, uint32_t cap) {
     return SPR_OK;
 }
 
+spr_status spr_render_set_spec_policy(spr_render *r, uint32_t policy) {
+    if (!r) return fail(SPR_E_INVALID, "null render");
+    if (policy != SPR_SPEC_UNIFORM && policy != SPR_SPEC_PER_RAY)
+        return fail(SPR_E_INVALID, "unknown speculation policy %u", policy);
+    if (r->started) return fail(SPR_E_STATE, "the speculation policy can only change before the first pass");
+    if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
+    spr_ctx *c = r->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    r->hreq.policy = policy;
+    HIPCHK(hipMemcpy(r->d_req, &r->hreq, sizeof(ReqDev), hipMemcpyHostToDevice));
+    return SPR_OK;
+}
+
 static spr_status fill_stats(spr_render *r, spr_pass_stats *o, float ms) {
     spr_ctx *c = r->ctx;
     ReqState s;
@@ -897,6 +923,7 @@ static spr_status fill_stats(spr_render *r, spr_pass_stats *o, float ms) {
     o->blocks_decoded = p.n_miss;
     o->deferred_pairs = s.last_deferred;
     o->terminated = s.last_terminated;
+    o->slots = s.last_slots;
     o->utilization = r->npix ? (double)s.last_pairs / (double)r->npix : 0.0;
     o->ms = ms;
     return SPR_OK;

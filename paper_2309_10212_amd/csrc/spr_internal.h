@@ -104,10 +104,31 @@ struct ReqState {
     uint32_t last_pairs, last_deferred, last_terminated, last_nspec;
     uint32_t entered;           // rays that entered the volume (set at the first pass)
     uint32_t segs;              // traversal lanes per active ray this pass (power of two, <= 16)
+    uint32_t slot_cursor;       // pair slots handed out this pass (per-ray counts: by the traversal)
+    uint32_t last_slots;        // pair slots of the last pass (the sum of the rays' counts)
     uint32_t pad[1];
     unsigned long long tot_pairs;
     unsigned long long bcmc;    // blocks whose fine range contains the isovalue (set up with the masks)
+    unsigned long long wsum;    // sum of the active rays' weights for the next pass (per-ray counts)
 };
+
+// Speculation policy of a render: one count for every ray (Sec. 4), or
+// per-ray counts from the rays' remaining paths.
+constexpr uint32_t SPEC_UNIFORM = 0, SPEC_PER_RAY = 1;
+
+// Weight of a ray whose remaining walk starts at t: its remaining path in
+// block lengths, 1 + floor((t_exit - t) / 4), and 1 once t >= t_exit.
+__device__ __forceinline__ uint32_t ray_weight(double t, double t_exit) {
+    return t < t_exit ? 1u + (uint32_t)floor((t_exit - t) * 0.25) : 1u;
+}
+
+// Per-ray count min(cap, 1 + floor((B - N) * w / W)): at least one slot per
+// ray, at most B over all N rays (W is the sum of their weights).
+__device__ __forceinline__ uint32_t nspec_ray(uint32_t B, uint32_t N, unsigned long long W, uint32_t w, uint32_t cap) {
+    const unsigned long long extra = (B > N && W) ? ((unsigned long long)(B - N) * w) / W : 0ull;
+    const unsigned long long n = 1ull + extra;
+    return n < cap ? (uint32_t)n : cap;
+}
 
 // Immutable per-render description (camera basis computed on the host).
 struct ReqDev {
@@ -117,6 +138,8 @@ struct ReqDev {
     uint32_t w, h, npix;
     uint32_t vol;               // index in the context's volume table
     uint32_t spec_cap;
+    uint32_t policy;            // SPEC_UNIFORM or SPEC_PER_RAY
+    uint32_t pad;
     uint32_t *ray_state;        // per pixel: last served block, RAY_NOT_STARTED, RAY_DONE
     uint32_t *act[2];           // compacted active pixel lists
     uint32_t *pair_blk;         // per pair slot (R_BID of Sec. 3.3/4.1)
@@ -126,6 +149,10 @@ struct ReqDev {
     uint32_t *nfound;           // per pixel: candidate blocks the traversal found this pass
     uint32_t *done_cnt;         // per pixel: the ray's pairs finished this pass (0 between passes)
     uint32_t *def_first;        // per pixel: first deferred slot of the ray this pass (NONE between passes)
+    uint32_t *rbase;            // per pixel: the ray's first pair slot this pass
+    uint32_t *rns;              // per pixel: the ray's speculation count this pass
+    uint32_t *rw;               // per pixel: the ray's weight this pass (per-ray counts)
+    uint32_t *pair_ray;         // per pair slot: active-ray index of its ray (per-ray counts)
     uint32_t *image;            // RGBA8 per pixel
     spr_hit *hits;              // per pixel
     ReqState *st;
@@ -186,6 +213,8 @@ struct Table {
                                 // and cleared by its compaction: {alive rays (initial-ray pass
                                 // only), pairs, deferred pairs, terminated rays}
     uint32_t *wave_off;         // exclusive prefix of the survivors
+    uint32_t *wave_w;           // per wave of the A space: summed weights of its rays for the next pass
+                                // (per-ray counts; cleared by the compaction like the records)
     uint32_t cap;               // request capacity
     uint32_t max_A;             // capacity of the A space (sum of padded npix)
     uint32_t max_P;             // capacity of the pair space (sum of npix)

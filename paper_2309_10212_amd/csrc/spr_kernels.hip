@@ -282,13 +282,21 @@ __global__ __launch_bounds__(64) void k_pass_begin(PassCtl *ctl, Table T, int is
         const uint32_t na = r0 == 0 ? na0 : (valid ? st->n_act : 0u);
         const uint32_t ns = r0 == 0 ? ns0 : (valid ? st->n_spec : 0u);
         const uint32_t ps = r0 == 0 ? ps0 : (valid ? st->passes : 0u);
-        const uint32_t segs = (na > 0 && ns <= TR_BUF) ? segs_all : 1u;
-        const uint32_t a = round64(na), at = round64(na * segs), pp = is_init ? 0u : na * ns;
+        const uint32_t pol = valid ? T.reqs[r].policy : SPEC_UNIFORM;
+        const uint32_t cap = valid ? T.reqs[r].spec_cap : 0u, npx = valid ? T.reqs[r].npix : 0u;
+        // per-ray counts: each ray's count is at most cap and they sum to at
+        // most w*h, so the request's slot space is the smaller of the two
+        const uint64_t pr_space = (uint64_t)na * cap < (uint64_t)npx ? (uint64_t)na * cap : (uint64_t)npx;
+        const bool seg_ok = pol == SPEC_PER_RAY ? cap <= TR_BUF : ns <= TR_BUF;
+        const uint32_t segs = (na > 0 && seg_ok) ? segs_all : 1u;
+        const uint32_t a = round64(na), at = round64(na * segs);
+        const uint32_t pp = is_init ? 0u : (pol == SPEC_PER_RAY ? (uint32_t)pr_space : na * ns);
         uint32_t ta, tat, tp, tr;
         const uint32_t ia = wave_incl_scan(a, &ta), iat = wave_incl_scan(at, &tat), ip = wave_incl_scan(pp, &tp);
         (void)wave_incl_scan(na, &tr);
         if (valid) {
             st->segs = segs;
+            st->slot_cursor = pol == SPEC_PER_RAY ? 0u : pp;   // per-ray counts: handed out by the traversal
             T.trav_base[r] = AT + iat - at;
             T.act_base[r] = A + ia - a;
             T.pair_base[r] = P + ip - pp;
@@ -413,10 +421,12 @@ __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
         const ReqDev &q = T.reqs[r];
         uint32_t i = p - T.act_base[r];
         bool alive = false;
+        uint32_t w = 0;
         if (i < q.npix) {
             Ray R;
             make_ray(q, vols[q.vol].n, i, R);
             alive = R.entered != 0;
+            w = alive ? ray_weight(R.te, R.tx) : 0u;
             q.ray_state[i] = alive ? RAY_NOT_STARTED : RAY_DONE;
             q.image[i] = 0u;
             spr_hit h;
@@ -430,7 +440,14 @@ __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
             q.def_first[i] = NONE;
         }
         uint64_t m = __ballot(alive);
-        if (lane_id() == 0) T.wave_rec[p >> 6] = make_uint4((uint32_t)__popcll(m), 0u, 0u, 0u);
+        // the entered rays' weights (per-ray speculation counts of the first
+        // pass); every lane of the wave is here
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) w += (uint32_t)__shfl_xor((int)w, off);
+        if (lane_id() == 0) {
+            T.wave_rec[p >> 6] = make_uint4((uint32_t)__popcll(m), 0u, 0u, 0u);
+            T.wave_w[p >> 6] = w;
+        }
     }
 }
 
@@ -454,7 +471,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         // request); ray i of the request runs on lanes i*L .. i*L+L-1
         const uint32_t r = uni(find_req(T.trav_base, nreq, p));
         const ReqDev &q = T.reqs[r];
-        const ReqState *st = uni(q.st);
+        ReqState *st = uni(q.st);
         const uint32_t L = uni(st->segs);
         const uint32_t local = p - uni(T.trav_base[r]);
         const uint32_t i = local >> __builtin_ctz(L);
@@ -466,7 +483,6 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         load_wave_req(q, vols[uni(q.vol)], u);
         const gptr<const uint64_t> cmask = as_global((const uint64_t *)uni(q.cmask64));
         const gptr<const uint8_t> cdist = as_global((const uint8_t *)uni(q.cdist));
-        const gptr<uint32_t> slots = as_global(uni(q.pair_blk) + (size_t)i * ns);
         const uint32_t state = uni(q.ray_state)[pix];
         Ray R;
         make_ray(u, u.n, pix, R);
@@ -500,6 +516,37 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
 #pragma unroll
             for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
         }
+        // The ray's speculation count and pair slots.  One count for every ray
+        // (Sec. 4): slots i*N_spec onwards.  Per-ray counts: the ray's weight
+        // from where its remaining walk starts (tcur, the same on every lane of
+        // a segment group), its count from the weight sum of the active rays,
+        // and its slots from the request's cursor, one atomic per wave (ranges
+        // of different rays may lie in any order; a ray's own slots stay
+        // consecutive and in walk order).
+        const uint32_t pol = uni(q.policy);
+        uint32_t nsr = ns, rbase_i = i * ns, wi = 0;
+        if (pol == SPEC_PER_RAY) {
+            wi = ray_weight(tcur, R.tx);
+            nsr = nspec_ray(uni(q.npix), uni(st->n_act_prev), uni((uint64_t)st->wsum), wi, uni(q.spec_cap));
+            const uint32_t v = seg == 0u ? nsr : 0u;
+            const uint64_t lt = lanemask_lt();
+            uint32_t before = 0, total = 0;
+#pragma unroll
+            for (int bit = 0; bit < 13; ++bit) {   // counts <= 4096: sums of bit planes over the lanes
+                const uint64_t bm = __ballot((v >> bit) & 1u);
+                before += (uint32_t)__popcll(bm & lt) << bit;
+                total += (uint32_t)__popcll(bm) << bit;
+            }
+            uint32_t base = 0;
+            if ((int)lane_id() == __ffsll((unsigned long long)__ballot(1)) - 1)
+                base = atomicAdd(&st->slot_cursor, total);
+            base = uni(base);
+            rbase_i = base + before;
+            if (L > 1u) rbase_i = (uint32_t)__shfl((int)rbase_i, (int)(lane_id() & ~(L - 1u)));
+        }
+        const gptr<uint32_t> slots = as_global(uni(q.pair_blk) + (size_t)rbase_i);
+        const gptr<uint32_t> pray = as_global(uni(q.pair_ray) + (size_t)rbase_i);
+        const bool per_ray = pol == SPEC_PER_RAY;
         // Segments (L > 1): the rest of the ray, [t_start, t_exit], is cut at
         // t_k = t_start + (t_exit - t_start) k / L; lane k lists the blocks whose
         // entry parameter lies in [t_k, t_k+1) (the first lane everything below
@@ -533,7 +580,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         // jump or a coarse step.  Inner loop: the blocks of a nonempty coarse
         // cell, no memory access but the LDS staging.
         bool guard_hit = false;
-        while (alive && found < ns) {
+        while (alive && found < nsr) {
             if (++steps > max_steps) { alive = false; guard_hit = true; break; }   // every step advances an index
             if (tcur >= t_hi && !fresh) { seg_done = true; break; }   // the rest is the next lane's
             const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
@@ -599,12 +646,15 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                     const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * u.nb[1] + cb[1]) * u.nb[0] + cb[0]);
                     s_slot[nbuf][threadIdx.x] = bid;
                     found++;
-                    if (++nbuf == TR_BUF && L == 1u) {   // segmented rays keep ns <= TR_BUF in LDS
-                        for (uint32_t k = 0; k < TR_BUF; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
+                    if (++nbuf == TR_BUF && L == 1u) {   // segmented rays keep their count <= TR_BUF in LDS
+                        for (uint32_t k = 0; k < TR_BUF; ++k) {
+                            slots[flushed + k] = s_slot[k][threadIdx.x];
+                            if (per_ray) pray[flushed + k] = i;
+                        }
                         flushed += TR_BUF;
                         nbuf = 0;
                     }
-                    if (found == ns) break;
+                    if (found == nsr) break;
                 }
                 if (++steps > max_steps) { alive = false; guard_hit = true; break; }
                 double tn = walk_exit(wb);
@@ -624,9 +674,12 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         // visible-list index 0, so it is always admitted and every pass makes
         // progress under the cache-capacity rule: reserve that index.
         if (L == 1u) {
-            for (uint32_t k = 0; k < nbuf; ++k) slots[flushed + k] = s_slot[k][threadIdx.x];
-            for (uint32_t k = found; k < ns; ++k) slots[k] = NONE;
-            if (found > 0 && T.pair_base[r] + i * ns == 0) ctl->n_vis = 1u;
+            for (uint32_t k = 0; k < nbuf; ++k) {
+                slots[flushed + k] = s_slot[k][threadIdx.x];
+                if (per_ray) pray[flushed + k] = i;
+            }
+            for (uint32_t k = found; k < nsr; ++k) slots[k] = NONE;
+            if (found > 0 && T.pair_base[r] + rbase_i == 0) ctl->n_vis = 1u;
         } else {
             // merge the lanes' lists in segment order: lane k's candidates go
             // after those of lanes 0..k-1; the first ns are the ray's slots
@@ -638,12 +691,15 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
             const uint32_t before = incl - found;
             const uint32_t total = (uint32_t)__shfl((int)incl, (int)(L - 1u), (int)L);
             for (uint32_t k = 0; k < found; ++k)
-                if (before + k < ns) slots[before + k] = s_slot[k][threadIdx.x];
+                if (before + k < nsr) {
+                    slots[before + k] = s_slot[k][threadIdx.x];
+                    if (per_ray) pray[before + k] = i;
+                }
             if (seg == 0u) {
-                for (uint32_t k = total < ns ? total : ns; k < ns; ++k) slots[k] = NONE;
-                if (total > 0 && T.pair_base[r] + i * ns == 0) ctl->n_vis = 1u;
+                for (uint32_t k = total < nsr ? total : nsr; k < nsr; ++k) slots[k] = NONE;
+                if (total > 0 && T.pair_base[r] + rbase_i == 0) ctl->n_vis = 1u;
             }
-            found = total < ns ? total : ns;   // the ray's candidates (every lane of the group)
+            found = total < nsr ? total : nsr;   // the ray's candidates (every lane of the group)
         }
         // The ray's outcome as far as the walk decides it: its candidate
         // count, which tells the pair that finishes the ray last how many to
@@ -656,6 +712,9 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         const bool term = lead && found == 0u;
         if (lead) {
             as_global(uni(q.nfound))[pix] = found;
+            as_global(uni(q.rbase))[pix] = rbase_i;
+            as_global(uni(q.rns))[pix] = nsr;
+            if (per_ray) as_global(uni(q.rw))[pix] = wi;
             if (term) as_global(uni(q.ray_state))[pix] = RAY_DONE;
         }
         uint32_t wpairs = 0;
@@ -704,7 +763,9 @@ __global__ __launch_bounds__(256) void k_dedupe(PassCtl *ctl, Table T, const Vol
             if (x < P) {
                 const uint32_t r = find_req(T.pair_base, nreq, x);
                 const ReqDev &q = T.reqs[r];
-                b[k] = q.pair_blk[x - T.pair_base[r]];
+                const uint32_t qq = x - T.pair_base[r];
+                // slots past the request's cursor were not handed out this pass
+                b[k] = qq < q.st->slot_cursor ? q.pair_blk[qq] : NONE;
                 vol[k] = q.vol;
             }
         }
@@ -993,11 +1054,14 @@ __global__ __launch_bounds__(256) void k_assign_scatter(PassCtl *ctl, Table T, c
         const uint32_t *const act = q.act[0], *const act1 = q.act[1];
         const uint32_t rank = W.pair_rank[x];
         const VolState V = vol_state(vols[q.vol]);
-        const uint32_t nsp = st->last_nspec, cur = st->cur;
+        const uint32_t nsp = st->last_nspec, cur = st->cur, used = st->slot_cursor;
+        const bool per_ray = q.policy == SPEC_PER_RAY;
+        const uint32_t *const pray = q.pair_ray;
+        if (qq >= used) continue;   // not handed out this pass (per-ray counts)
         const uint32_t b = pblk[qq];
         if (b == NONE) continue;
         const uint32_t vi = V.vis_idx[bidx(V, b)];
-        const uint32_t ii = qq / nsp;
+        const uint32_t ii = per_ray ? pray[qq] : qq / nsp;
         const uint32_t pix = (cur ? act1 : act)[ii];
         if (vi >= vadm) {
             // a pair on a block not served this pass (cache-capacity rule):
@@ -1006,15 +1070,18 @@ __global__ __launch_bounds__(256) void k_assign_scatter(PassCtl *ctl, Table T, c
             // ray is deferred, nothing is raytraced and the ray stays as it
             // was, so the last of them resets the ray's pass state here.
             uint32_t *const dfirst = q.def_first, *const dcnt = q.done_cnt;
-            const uint32_t nf = q.nfound[pix];
-            uint4 *const rec = T.wave_rec + ((T.act_base[r] + ii) >> 6);
-            atomicMin(dfirst + pix, qq - ii * nsp);
+            const uint32_t nf = q.nfound[pix], rb = q.rbase[pix];
+            const uint32_t wave = (T.act_base[r] + ii) >> 6;
+            uint4 *const rec = T.wave_rec + wave;
+            atomicMin(dfirst + pix, qq - rb);
             atomicAdd(&rec->z, 1u);
             // acquire-release: the minimum above is visible to whichever pair
             // finishes the ray, and that pair sees every other pair's
             if (__hip_atomic_fetch_add(dcnt + pix, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == nf) {
                 dcnt[pix] = 0u;
                 dfirst[pix] = NONE;
+                // the ray stays where it was: same weight next pass
+                if (per_ray) atomicAdd(T.wave_w + wave, q.rw[pix]);
             }
             continue;
         }
@@ -1091,18 +1158,20 @@ __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols,
 //     walk found fewer than N_spec blocks (it left the volume), and else
 //     resumes after its last candidate.
 // The ray's per-pixel pass state is reset for the next pass.
-__device__ __forceinline__ void finish_ray(const Table &T, uint32_t r, uint32_t pix, uint32_t qq) {
+__device__ __forceinline__ void finish_ray(const Table &T, const VolDev *vols, uint32_t r, uint32_t pix, uint32_t qq) {
     const ReqDev &q = T.reqs[r];
     uint64_t *const bestp = q.best;
     uint32_t *const ray_state = q.ray_state, *const pblk = q.pair_blk;
     uint32_t *const dcnt = q.done_cnt, *const dfirst = q.def_first;
-    const uint32_t ns = q.st->last_nspec;
-    const uint32_t i = qq / ns, base = i * ns;
+    const bool per_ray = q.policy == SPEC_PER_RAY;
+    const uint32_t base = q.rbase[pix], ns = q.rns[pix];
+    const uint32_t i = per_ray ? q.pair_ray[qq] : qq / ns;
     const uint32_t nf = q.nfound[pix];
     const uint64_t best = __hip_atomic_load(bestp + pix, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t d = __hip_atomic_load(dfirst + pix, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t kb = best != ~0ull ? (uint32_t)(best >> 38) - base : NONE;
     bool term = false;
+    uint32_t next = NONE;   // the block the ray resumes after, if it moved
     if (kb != NONE && kb < d) {
         q.image[pix] = (uint32_t)best;
         spr_hit h;
@@ -1112,15 +1181,35 @@ __device__ __forceinline__ void finish_ray(const Table &T, uint32_t r, uint32_t 
         q.hits[pix] = h;
         term = true;
     } else if (d != NONE) {
-        if (d > 0u) ray_state[pix] = pblk[base + d - 1u];
+        if (d > 0u) next = pblk[base + d - 1u];
     } else if (nf < ns) {
         term = true;
     } else {
-        ray_state[pix] = pblk[base + nf - 1u];
+        next = pblk[base + nf - 1u];
     }
+    const uint32_t wave = (T.act_base[r] + i) >> 6;
     if (term) {
         ray_state[pix] = RAY_DONE;
-        atomicAdd(&T.wave_rec[(T.act_base[r] + i) >> 6].w, 1u);
+        atomicAdd(&T.wave_rec[wave].w, 1u);
+    } else {
+        if (next != NONE) ray_state[pix] = next;
+        if (per_ray) {
+            // the survivor's weight for the next pass: from where it leaves
+            // the block it resumes after (the traversal's restart point)
+            uint32_t w = q.rw[pix];
+            if (next != NONE) {
+                const VolDev &V = vols[q.vol];
+                Ray R;
+                make_ray(q, V.n, pix, R);
+                const Level LB = {4, {V.tb[0], V.tb[1], V.tb[2]}, {V.n[0], V.n[1], V.n[2]}, 0.25};
+                const int cb[3] = {(int)(next % (uint32_t)V.nb[0]), (int)((next / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]),
+                                   (int)(next / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]))};
+                AxisWalk wb;
+                walk_init(R, LB, cb, wb);
+                w = ray_weight(walk_exit(wb), R.tx);
+            }
+            atomicAdd(T.wave_w + wave, w);
+        }
     }
     if (best != ~0ull) bestp[pix] = ~0ull;
     dcnt[pix] = 0u;
@@ -1302,7 +1391,7 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
             // and its traversal state for the next pass.
             const uint32_t nf = q.nfound[pix];
             if (__hip_atomic_fetch_add(q.done_cnt + pix, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == nf)
-                finish_ray(T, r, pix, qq);
+                finish_ray(T, vols, r, pix, qq);
         }
         __syncthreads();   // the next tile reuses the LDS
     }
@@ -1323,14 +1412,26 @@ constexpr int PE_THREADS = 1024;
 
 __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, int is_init) {
     __shared__ uint32_t s_req[4][MAX_REQS];   // survivors, pairs, deferred, terminated
+    __shared__ unsigned long long s_wsum[MAX_REQS];   // survivors' weights (per-ray counts)
     __shared__ uint32_t s_wave[PE_THREADS / 64];
     const uint32_t nw = ctl->A >> 6;
     const uint32_t nreq = ctl->nreq;
     const uint32_t t = threadIdx.x;
     for (uint32_t r = t; r < nreq; r += PE_THREADS) {
         s_req[0][r] = 0; s_req[1][r] = 0; s_req[2][r] = 0; s_req[3][r] = 0;
+        s_wsum[r] = 0;
     }
     __syncthreads();
+    // the survivors' weights, per request (thread-strided over the waves)
+    if (nw > 0) {
+        uint32_t r = find_req(T.act_base, nreq, (t < nw ? t : 0u) << 6);
+        for (uint32_t w = t; w < nw; w += PE_THREADS) {
+            const uint32_t ww = T.wave_w[w];
+            if (!ww) continue;
+            while (r + 1 < nreq && T.act_base[r + 1] <= (w << 6)) ++r;
+            atomicAdd(&s_wsum[r], (unsigned long long)ww);
+        }
+    }
     const uint32_t per = (nw + PE_THREADS - 1) / PE_THREADS;
     const uint32_t w0 = t * per < nw ? t * per : nw;
     const uint32_t w1 = w0 + per < nw ? w0 + per : nw;
@@ -1457,6 +1558,8 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
         const uint32_t na = s_req[0][r];
         if (st->n_act_prev > 0) st->cur ^= 1u;
         st->n_act = na;
+        st->wsum = s_wsum[r];
+        st->last_slots = is_init ? 0u : st->slot_cursor;
         st->last_pairs = s_req[1][r];
         st->last_deferred = s_req[2][r];
         st->last_terminated = s_req[3][r];
@@ -1494,7 +1597,10 @@ __global__ __launch_bounds__(256) void k_compact(PassCtl *ctl, Table T) {
         }
         // the pass's wave records are consumed: clear them for the next pass
         // (whose active-ray space is no larger than this one's)
-        if (lane_id() == 0) T.wave_rec[p >> 6] = make_uint4(0u, 0u, 0u, 0u);
+        if (lane_id() == 0) {
+            T.wave_rec[p >> 6] = make_uint4(0u, 0u, 0u, 0u);
+            T.wave_w[p >> 6] = 0u;
+        }
     }
 }
 

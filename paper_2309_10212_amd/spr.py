@@ -22,6 +22,7 @@ ERRORS = {-1: "SPR_E_INVALID", -2: "SPR_E_OOM", -3: "SPR_E_HIP", -4: "SPR_E_CORR
 NONE = 0xFFFFFFFF
 DTYPE_F32, DTYPE_U8 = 0, 1
 CODEC_VERSION = 1
+SPEC_UNIFORM, SPEC_PER_RAY = 0, 1
 
 
 class SprError(RuntimeError):
@@ -57,14 +58,14 @@ class PassStats(ctypes.Structure):
     _fields_ = [("pass_", ctypes.c_uint32), ("n_active", ctypes.c_uint32), ("n_spec", ctypes.c_uint32),
                 ("pairs", ctypes.c_uint32), ("visible_blocks", ctypes.c_uint32), ("active_blocks", ctypes.c_uint32),
                 ("blocks_decoded", ctypes.c_uint32), ("deferred_pairs", ctypes.c_uint32),
-                ("terminated", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("utilization", ctypes.c_double),
+                ("terminated", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("utilization", ctypes.c_double),
                 ("ms", ctypes.c_float), ("pad", ctypes.c_float)]
 
     def as_dict(self):
         return {"pass": self.pass_, "n_active": self.n_active, "n_spec": self.n_spec, "pairs": self.pairs,
                 "visible": self.visible_blocks, "active_blocks": self.active_blocks,
                 "blocks_decoded": self.blocks_decoded, "deferred": self.deferred_pairs,
-                "terminated": self.terminated, "utilization": self.utilization, "ms": self.ms}
+                "terminated": self.terminated, "slots": self.slots, "utilization": self.utilization, "ms": self.ms}
 
 
 class Counters(ctypes.Structure):
@@ -134,6 +135,7 @@ SIGNATURES = [
     ("spr_debug_fp64_ops", _ST, [_P, _P, _P, ctypes.c_size_t, _P, _P]),
     ("spr_render_begin", _ST, [_P, ctypes.POINTER(_Camera), ctypes.c_float, _U32, _U32, ctypes.POINTER(_P)]),
     ("spr_render_set_spec_cap", _ST, [_P, _U32]),
+    ("spr_render_set_spec_policy", _ST, [_P, _U32]),
     ("spr_render_pass", _ST, [_P, ctypes.POINTER(PassStats)]),
     ("spr_render_done", _ST, [_P, ctypes.POINTER(ctypes.c_int)]),
     ("spr_render_run", _ST, [_P, _U32, ctypes.POINTER(_U32)]),
@@ -354,7 +356,8 @@ class Volume:
 class Render:
     """One camera/isovalue request rendered progressively (spr_render)."""
 
-    def __init__(self, vol: Volume, cam, iso: float, w: int, h: int, spec_cap: int | None = None):
+    def __init__(self, vol: Volume, cam, iso: float, w: int, h: int, spec_cap: int | None = None,
+                 policy: int = 0):
         self.vol = vol
         self.w, self.h = int(w), int(h)
         c = _cam(cam)
@@ -364,6 +367,12 @@ class Render:
         self.h_ = hh
         if spec_cap is not None:
             self.set_spec_cap(spec_cap)
+        if policy:
+            self.set_spec_policy(policy)
+
+    def set_spec_policy(self, policy: int):
+        """SPEC_UNIFORM (Sec. 4's single count) or SPEC_PER_RAY (per-ray counts)."""
+        _chk(load_library().spr_render_set_spec_policy(self.h_, int(policy)), "spr_render_set_spec_policy")
 
     def set_spec_cap(self, cap: int):
         _chk(load_library().spr_render_set_spec_cap(self.h_, int(cap)), "spr_render_set_spec_cap")

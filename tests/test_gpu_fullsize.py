@@ -55,20 +55,22 @@ def test_fullsize_grids_decode_and_render(fourier):
         ids = np.arange(b0, min(vol.nblocks, b0 + (1 << 20)), dtype=np.uint32)
         assert np.array_equal(vol.decode_blocks(ids).view(np.uint32),
                               oracle.decode_blocks(s, (N, N, N), RATE, ids).view(np.uint32)), b0
-    for k, cap in ((0, 16), (5, 1), (7, 64)):
-        r = spr.Render(vol, cams[k], iso, W, H, spec_cap=cap)
+    for k, cap, pol in ((0, 16, 0), (5, 1, 0), (7, 64, 0), (3, 64, 1)):
+        r = spr.Render(vol, cams[k], iso, W, H, spec_cap=cap, policy=pol)
         got = []
         while not r.done():
             got.append(r.pass_(stats=True))
             assert len(got) < 500
-        sched = oracle.schedule(dec, cams[k], iso, W, H, cap)
+        sched = oracle.schedule(dec, cams[k], iso, W, H, cap, policy=pol)
         assert len(got) == len(sched), (k, cap, len(got), len(sched))
+        keys = ("n_active", "slots", "pairs", "visible", "active_blocks", "terminated") if pol else \
+            ("n_active", "n_spec", "slots", "pairs", "visible", "active_blocks", "terminated")
         for p, (g, o) in enumerate(zip(got, sched)):
-            for key in ("n_active", "n_spec", "pairs", "visible", "active_blocks", "terminated"):
-                assert g[key] == o[key], (k, cap, p, key, g, o)
+            for key in keys:
+                assert g[key] == o[key], (k, cap, pol, p, key, g, o)
         dt = _cmp(r.hits(), r.image(), oracle.render(dec, cams[k], iso, W, H), f"view {k} cap {cap}")
         assert r.info()["bcmc_blocks"] == oracle.blocks_containing(rf, iso)
-        print(f"view {k} cap {cap}: {len(got)} passes, max |dt| {dt:.3g}", flush=True)
+        print(f"view {k} cap {cap} policy {pol}: {len(got)} passes, max |dt| {dt:.3g}", flush=True)
         r.free()
     vol.free()
     ctx.close()

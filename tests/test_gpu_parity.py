@@ -323,3 +323,64 @@ def test_batch_equals_alone(ctx):
         r.free()
     for v, _ in vols:
         v.free()
+
+
+@pytest.mark.parametrize("cap", [16, 64])
+def test_per_ray_speculation_counters_and_image(ctx, cap):
+    """Per-ray speculation counts: every per-pass counter (active rays, slots
+    handed out, pairs, visible and active blocks, terminated rays) equals the
+    oracle's per-ray schedule, and the image equals the oracle's (and so the
+    single-count image)."""
+    from paper_2309_10212_amd import spr
+    s, dec, cam = _tiny()
+    n, w, h, iso = 64, 256, 256, 0.5
+    vol = ctx.load_volume(s, (n, n, n), 8)
+    r = spr.Render(vol, cam, iso, w, h, spec_cap=cap, policy=spr.SPEC_PER_RAY)
+    sched = oracle.schedule(dec, cam, iso, w, h, cap, policy=oracle.POLICY_PER_RAY)
+    got = []
+    while not r.done():
+        got.append(r.pass_(stats=True))
+        assert len(got) <= len(sched) + 2
+    assert len(got) == len(sched), (len(got), len(sched))
+    for p, (g, o) in enumerate(zip(got, sched)):
+        for k in ("n_active", "slots", "pairs", "visible", "active_blocks", "terminated"):
+            assert g[k] == o[k], (p, k, g, o)
+    _cmp_hits(r.hits(), r.image(), oracle.render(dec, cam, iso, w, h), f"per-ray cap={cap}")
+    r.free()
+    # a batch mixing both policies equals the renders alone
+    rs = [spr.Render(vol, cam, iso, 128, 96, spec_cap=cap, policy=pol) for pol in (spr.SPEC_PER_RAY, spr.SPEC_UNIFORM)]
+    b = spr.Batch(ctx, rs)
+    b.run()
+    outs = [(x.hits(), x.image()) for x in rs]
+    b.free()
+    for x in rs:
+        x.free()
+    for pol, (hb, ib) in zip((spr.SPEC_PER_RAY, spr.SPEC_UNIFORM), outs):
+        ra = spr.Render(vol, cam, iso, 128, 96, spec_cap=cap, policy=pol)
+        ra.run()
+        assert np.array_equal(ra.hits().view(np.uint8), hb.view(np.uint8)) and np.array_equal(ra.image(), ib)
+        ra.free()
+    vol.free()
+
+
+def test_per_ray_speculation_sparse_volume(ctx):
+    from paper_2309_10212_amd import spr
+    n = 256
+    f = volgen.blobs(n, n, n, seed=21, nblob=2)
+    s = volgen.encode(f, 8)
+    dec = oracle.decode_volume(s, (n, n, n), 8)
+    vol = ctx.load_volume(s, (n, n, n), 8)
+    cam = volgen.orbit_camera(n, n, n, seed=22)
+    r = spr.Render(vol, cam, 0.3, 160, 120, spec_cap=8, policy=spr.SPEC_PER_RAY)   # cap <= 16: segmented walks
+    got = []
+    while not r.done():
+        got.append(r.pass_(stats=True))
+        assert len(got) < 400
+    sched = oracle.schedule(dec, cam, 0.3, 160, 120, 8, policy=oracle.POLICY_PER_RAY)
+    assert len(got) == len(sched)
+    for p, (g, o) in enumerate(zip(got, sched)):
+        for key in ("n_active", "slots", "pairs", "visible", "active_blocks", "terminated"):
+            assert g[key] == o[key], (p, key, g, o)
+    _cmp_hits(r.hits(), r.image(), oracle.render(dec, cam, 0.3, 160, 120), "sparse per-ray")
+    r.free()
+    vol.free()
