@@ -242,6 +242,21 @@ spr_status spr_volume_ranges(spr_volume *vol, float *fine_lohi, size_t fine_coun
  * (SPR_E_OOM if it fails).  Synchronises. */
 spr_status spr_debug_decode_blocks(spr_volume *vol, const uint32_t *ids, uint32_t n, float *host_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * decode as spr_debug_decode_blocks, with the same arguments, ownership and
+ * output, and no allocation.  Its device staging (the n block ids and their
+ * n*64 decoded floats) is a fixed buffer that the library holds per GPU from
+ * the first context created on that GPU until the process ends
+ * (SPR_NOALLOC_MAX_BLOCKS * 260 bytes, 4.06 MiB plus alignment).  Every call
+ * on one GPU shares that buffer, which keeps the last call's contents, so
+ * calls that overlap on one GPU (several threads, or contexts on different
+ * streams) race; calls from one thread at a time are safe.  SPR_E_CAPACITY
+ * for n > SPR_NOALLOC_MAX_BLOCKS, SPR_E_INVALID for an id outside the volume
+ * (both checked before any device work).  Synchronises. */
+#define SPR_NOALLOC_MAX_BLOCKS 16384u
+spr_status spr_debug_decode_blocks_noalloc(spr_volume *vol, const uint32_t *ids, uint32_t n, float *host_out);
+
 /* Debug/parity: sqrt(x[i]) and x[i] / y[i] in fp64 on the device, compiled
  * exactly like the hit test (which relies on IEEE correctly rounded fp64
  * division and square root); n values, host arrays.  Synchronises. */

@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -59,6 +60,41 @@ enum MemCat {
 
 }  // namespace
 
+// Staging of the allocation-free decode (spr_debug_decode_blocks_noalloc):
+// the block ids at offset 0, the decoded values at NOALLOC_OUT_OFF.  Each GPU
+// holds its own copy for the life of the process.  In host code `scratch`
+// names a host-side stand-in, not the device copy: kernels and copies take
+// the address hipGetSymbolAddress returns for the current device
+// (scratch_ptr below), never the array's name.
+namespace {
+constexpr size_t NOALLOC_OUT_OFF = ((size_t)SPR_NOALLOC_MAX_BLOCKS * sizeof(uint32_t) + 255) & ~(size_t)255;
+constexpr size_t NOALLOC_BYTES = NOALLOC_OUT_OFF + (size_t)SPR_NOALLOC_MAX_BLOCKS * 64 * sizeof(float);
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (the caller has made it current).
+spr_status scratch_ptr(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return fail(SPR_E_INVALID, "device %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SPR_E_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return SPR_OK;
+}
+}  // namespace
+
 struct spr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -92,6 +128,7 @@ struct spr_ctx {
     double prof_ms[PROF_SLOTS] = {};
     uint64_t prof_n[PROF_SLOTS] = {};
     void *pinned = nullptr;     // small host staging area
+    void *noalloc = nullptr;    // this device's copy of the allocation-free decode's staging
     int n_renders = 0;
 };
 
@@ -442,6 +479,10 @@ spr_status spr_ctx_create(const spr_config *cfg, spr_ctx **out) {
         spr_ctx_destroy(c);
         return fail(SPR_E_HIP, "hipEventCreate failed");
     }
+    if ((st = scratch_ptr(c->device, &c->noalloc)) != SPR_OK) {
+        spr_ctx_destroy(c);
+        return st;
+    }
     PassCtl h{};
     h.n_slots = (uint32_t)slots;
     h.free_top = (uint32_t)slots;
@@ -744,6 +785,27 @@ spr_status spr_debug_decode_blocks(spr_volume *v, const uint32_t *ids, uint32_t 
     dfree(c, MEM_SCRATCH, d_ids, n);
     dfree(c, MEM_SCRATCH, d_out, (size_t)n * 64);
     if (e != hipSuccess) return fail(SPR_E_HIP, "debug decode failed: %s", hipGetErrorString(e));
+    return SPR_OK;
+}
+
+spr_status spr_debug_decode_blocks_noalloc(spr_volume *v, const uint32_t *ids, uint32_t n, float *host_out) {
+    if (!v || (!ids && n) || (!host_out && n)) return fail(SPR_E_INVALID, "null argument");
+    if (n > SPR_NOALLOC_MAX_BLOCKS)
+        return fail(SPR_E_CAPACITY, "%u blocks exceed the allocation-free limit of %u", n, SPR_NOALLOC_MAX_BLOCKS);
+    if (n == 0) return SPR_OK;
+    spr_ctx *c = v->ctx;
+    const VolDev &V = c->h_vols[v->idx];
+    for (uint32_t i = 0; i < n; ++i)
+        if (ids[i] >= V.nblocks) return fail(SPR_E_INVALID, "block id %u out of range", ids[i]);
+    HIPCHK(hipSetDevice(c->device));
+    // c->noalloc was looked up for this device when the context was created
+    uint32_t *d_ids = (uint32_t *)c->noalloc;
+    float *d_out = (float *)((unsigned char *)c->noalloc + NOALLOC_OUT_OFF);
+    hipError_t e = hipMemcpyAsync(d_ids, ids, n * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_decode_ids(c->stream, V, d_ids, n, d_out);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_out, d_out, (size_t)n * 64 * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(SPR_E_HIP, "allocation-free decode failed: %s", hipGetErrorString(e));
     return SPR_OK;
 }
 

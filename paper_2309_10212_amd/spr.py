@@ -22,6 +22,7 @@ ERRORS = {-1: "SPR_E_INVALID", -2: "SPR_E_OOM", -3: "SPR_E_HIP", -4: "SPR_E_CORR
 NONE = 0xFFFFFFFF
 DTYPE_F32, DTYPE_U8 = 0, 1
 CODEC_VERSION = 1
+NOALLOC_MAX_BLOCKS = 16384   # SPR_NOALLOC_MAX_BLOCKS
 SPEC_UNIFORM, SPEC_PER_RAY = 0, 1
 
 
@@ -132,6 +133,7 @@ SIGNATURES = [
     ("spr_volume_build_grids", _ST, [_P]),
     ("spr_volume_ranges", _ST, [_P, _P, ctypes.c_size_t, _P, ctypes.c_size_t]),
     ("spr_debug_decode_blocks", _ST, [_P, _P, _U32, _P]),
+    ("spr_debug_decode_blocks_noalloc", _ST, [_P, _P, _U32, _P]),
     ("spr_debug_fp64_ops", _ST, [_P, _P, _P, ctypes.c_size_t, _P, _P]),
     ("spr_render_begin", _ST, [_P, ctypes.POINTER(_Camera), ctypes.c_float, _U32, _U32, ctypes.POINTER(_P)]),
     ("spr_render_set_spec_cap", _ST, [_P, _U32]),
@@ -345,6 +347,15 @@ class Volume:
         out = np.empty((len(ids), 64), np.float32)
         _chk(load_library().spr_debug_decode_blocks(self.h, _ptr(ids), len(ids), _ptr(out)),
              "spr_debug_decode_blocks")
+        return out
+
+    def decode_blocks_noalloc(self, ids) -> np.ndarray:
+        """decode_blocks through the allocation-free entry point (at most
+        NOALLOC_MAX_BLOCKS ids)."""
+        ids = np.ascontiguousarray(ids, np.uint32)
+        out = np.empty((len(ids), 64), np.float32)
+        _chk(load_library().spr_debug_decode_blocks_noalloc(self.h, _ptr(ids), len(ids), _ptr(out)),
+             "spr_debug_decode_blocks_noalloc")
         return out
 
     def free(self):
