@@ -50,7 +50,7 @@ RM_NAME = "rm2048x2048x1920_rate2_1280x720"
 TRAFFIC_FILES = {"rm": os.path.join(ROOT, "profiles", f"hbm_traffic_{RM_NAME}.txt"),
                  "fourier": os.path.join(ROOT, "profiles", "hbm_traffic_fourier512_rate4_1280x720.txt")}
 PASS_KERNELS = ("k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_evict_hist",
-                "k_evict", "k_assign_scatter", "k_decode", "k_raytrace", "k_pass_end", "k_compact")
+                "k_evict", "k_assign_scatter", "k_decode", "k_raytrace", "k_finish", "k_pass_end", "k_compact")
 
 
 def log(*a):
@@ -71,16 +71,21 @@ def kernel_bytes(name, c, rate):
         "k_block_ranges": (8 * rate + 8) * NB,     # record in, own range out
         "k_fine_grid": 48 * NB,                    # three in-place axis passes: range in and out each
         "k_coarse_grid": 8 * NB + 8 * NC,          # fine ranges in, coarse range out
-        "k_iso_masks": 8 * c.get("mask_blocks", NB) + 16 * c.get("mask_coarse", NC),   # fine + coarse ranges in, mask word out
-        "k_init_rays": 44 * NP,                    # ray state, image, hit record, active entry, pass state
-        "k_traverse": 12 * A + 4 * S + 8 * V,      # + each ray's candidate count
+        # coarse range in, mask word and distance seed out, the three distance passes (1 B in, 1 B out each);
+        # the fine ranges of the coarse cells whose range contains the isovalue (64 blocks each)
+        "k_iso_masks": 23 * c.get("mask_coarse", NC) + 8 * c.get("mask_blocks", NB),
+        "k_init_rays": 40 * NP,                    # ray state, image, hit record, active entry, pass state
+        "k_traverse": 20 * A + 4 * S + 8 * V,      # active entry + state in; candidate count, slot base, count out
         "k_dedupe": 4 * S + 12 * P + 12 * V,
         "k_mark": 52 * V + 12 * K + 8 * M,      # + the 8 neighbour stamps each visible block tests
         "k_assign_scatter": 32 * M + 4 * S + 28 * Ps,
         "k_decode": (8 * rate + 268) * M + 64 * V,   # + each visible block's 8 neighbour slots, read and listed
-        # per served pair: sorted entry, visible entry, hit t and key, its ray's pair count and finish counter;
-        # per visible block: the staged dual grid and its 8 slot ids; per ray: the finish (composite) by its last pair
-        "k_raytrace": 48 * Ps + 532 * V + 60 * A,
+        # per served pair: sorted entry (12 B), hit t and key (16 B, hits only: an upper bound); per visible
+        # block: its 5^3 dual grid once, its 8 slot ids and its list entry
+        "k_raytrace": 28 * Ps + 540 * V,
+        # per active ray: list entry, candidate count, best key, deferral, slot base and count, and for a hit
+        # its t, block, image and hit record, ray state (an upper bound)
+        "k_finish": 64 * A,
         "k_compact": 12 * A,
     }
     return model.get(name)
@@ -93,7 +98,7 @@ def hbm_fractions(c, rate, steps, ms_per_step, passes, decoded, decode_ms, peak_
     against it, blocks decoded/s against 8 TB/s over a decode's bytes per
     block, peak memory against the 288 GB of HBM."""
     names = ("k_block_ranges", "k_fine_grid", "k_coarse_grid", "k_iso_masks", "k_init_rays", "k_traverse", "k_dedupe",
-             "k_mark", "k_assign_scatter", "k_decode", "k_raytrace", "k_compact")
+             "k_mark", "k_assign_scatter", "k_decode", "k_raytrace", "k_finish", "k_compact")
     byts = sum(kernel_bytes(k, c, rate) or 0 for k in names) / max(steps, 1)
     t_floor_ms = byts / (HBM_PEAK_GBS * 1e9) * 1e3
     frac_t = t_floor_ms / ms_per_step if ms_per_step > 0 else None
@@ -389,7 +394,8 @@ def run_rm(args):
     value = rays / el
     nb_vol = (RM_DIMS[0] // 4) * (RM_DIMS[1] // 4) * (RM_DIMS[2] // 4)
     nc_vol = ((RM_DIMS[0] // 4 + 3) // 4) * ((RM_DIMS[1] // 4 + 3) // 4) * ((RM_DIMS[2] // 4 + 3) // 4)
-    extra_counts = {"load_blocks": 0, "load_coarse": 0, "mask_blocks": nb_vol * steps, "mask_coarse": nc_vol * steps,
+    extra_counts = {"load_blocks": 0, "load_coarse": 0, "mask_coarse": nc_vol * steps,
+                    "mask_blocks": 64 * sum(i["iso_coarse_cells"] for i in infos),
                     "setup_pixels": w * h * steps}
     dc.update(extra_counts)
     log(f"[bench] plain: {steps} requests, {value / 1e6:.1f} M rays/s, {el * 1e3 / steps:.3f} ms per request, "
@@ -620,7 +626,8 @@ def run_fourier(args):
     el = time.perf_counter() - t0
     dc = _counter_delta(c0, ctx.counters())
     dc.update({"load_blocks": 0, "load_coarse": 0, "setup_pixels": args.w * args.h * args.steps,
-               "mask_blocks": ((n + 3) // 4) ** 3 * args.steps, "mask_coarse": ((((n + 3) // 4) + 3) // 4) ** 3 * args.steps})
+               "mask_blocks": 64 * sum(i["iso_coarse_cells"] for i in infos),
+               "mask_coarse": ((((n + 3) // 4) + 3) // 4) ** 3 * args.steps})
     ktimes, dcp, prof_ms = {}, dc, None
     if not args.no_profile:
         vol.free()

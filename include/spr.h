@@ -150,6 +150,8 @@ typedef struct {
     uint64_t pairs;           /* ray-block pairs over all passes */
     uint64_t bcmc_blocks;     /* blocks whose fine range contains the isovalue: what decompressing every
                                  block that may hold the surface (the BCMC comparison, Sec. 5) decodes */
+    uint64_t iso_coarse_cells; /* coarse cells whose range contains the isovalue (Sec. 3.1): the ones whose
+                                 blocks' fine ranges the isovalue masks read */
 } spr_render_info;
 
 /* Accumulated device time of one kernel of the pass (profiling mode). */
@@ -204,8 +206,10 @@ spr_status spr_ctx_kernel_times(spr_ctx *ctx, spr_kernel_time *out, uint32_t max
 /* Launch tuning of the block raytrace (Sec. 3.7, Sec. 4.3), for batching and
  * the autotuner: each workgroup takes pairs_per_wg sorted pairs (128 or 256)
  * and stages the dual grids of up to slot_tile distinct blocks in LDS (16 or
- * 32).  The image does not depend on either.  Applies to passes enqueued
- * after the call (captured pass graphs are re-recorded).  Defaults 256 / 32.
+ * 32); slot_tile 0 stages nothing: each pair reads its cells' corners from
+ * the cache slots, the next cell's while the current one is tested.  The
+ * image does not depend on either.  Applies to passes enqueued after the
+ * call (captured pass graphs are re-recorded).  Defaults 256 / 0.
  * SPR_E_INVALID for other values. */
 typedef struct {
     uint32_t pairs_per_wg;

@@ -2,7 +2,8 @@
 
 Chooses, for a set of render requests run as one batch, the speculation cap
 (Sec. 4: N_spec = clamp(floor(w*h / N_act), 1, cap)) and the block-raytrace
-launch tuning (sorted pairs per workgroup, blocks staged in LDS per tile).
+launch tuning (sorted pairs per workgroup, blocks staged in LDS per tile, or
+no staging: each pair reads its corners from the cache slots).
 None of these changes an image; they trade passes against per-pass work and
 occupancy.  The tuner renders a seeded sample of the requests as one batch
 under every candidate, after one untimed warm-up run so that every candidate
@@ -20,7 +21,7 @@ import numpy as np
 from . import spr
 
 DEFAULT_CAPS = (4, 8, 16, 32, 64)
-DEFAULT_TILES = ((128, 16), (128, 32), (256, 16), (256, 32))
+DEFAULT_TILES = ((256, 0), (128, 16), (128, 32), (256, 16), (256, 32))
 
 
 @dataclass

@@ -100,7 +100,7 @@ struct spr_ctx {
     hipStream_t stream = nullptr;
     spr_allocator alloc{};
     uint32_t spec_cap = 64;
-    uint32_t rt_tile = 256, rt_lb = 32;   // raytrace launch tuning (spr_ctx_set_tuning)
+    uint32_t rt_tile = 256, rt_lb = 0;    // raytrace launch tuning (spr_ctx_set_tuning)
     size_t mem_cur = 0, mem_peak = 0;
     size_t mem_cat[MEM_NCAT] = {}, mem_cat_peak[MEM_NCAT] = {}, mem_at_peak[MEM_NCAT] = {};
     PassCtl *ctl = nullptr;
@@ -300,6 +300,7 @@ spr_status ensure_work(spr_ctx *c, uint64_t P) {
     dfree(c, MEM_SCRATCH, W.pair_rank, oP); dfree(c, MEM_SCRATCH, W.s_ray, oP); dfree(c, MEM_SCRATCH, W.s_q, oP); dfree(c, MEM_SCRATCH, W.s_vi, oP);
     dfree(c, MEM_SCRATCH, W.vis_nsl, 8 * oP);
     W.cap_P = 0; W.cap_K = 0;
+    if (!W.seg_buf) CHK(dalloc(c, MEM_SCRATCH, (size_t)SEG_BIG_NS * SEG_BIG_LANES, &W.seg_buf));
     uint64_t cP = P, cK = 8 * P;
     CHK(dalloc(c, MEM_SCRATCH, cP, &W.vis_list)); CHK(dalloc(c, MEM_SCRATCH, cP, &W.vis_off));
     CHK(dalloc(c, MEM_SCRATCH, cK, &W.miss_list)); CHK(dalloc(c, MEM_SCRATCH, cK, &W.miss_slot));
@@ -319,6 +320,7 @@ spr_status alloc_table(spr_ctx *c, MemCat cat, uint32_t cap, uint64_t max_A, uin
     CHK(dalloc(c, cat, cap + 1, &T.act_base));
     CHK(dalloc(c, cat, cap + 1, &T.pair_base));
     CHK(dalloc(c, cat, cap + 1, &T.trav_base));
+    CHK(dalloc(c, cat, cap + 1, &T.big_base));
     CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_rec));
     CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_off));
     CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_w));
@@ -334,6 +336,7 @@ void free_table(spr_ctx *c, MemCat cat, Table &T) {
     dfree(c, cat, T.act_base, T.cap + 1);
     dfree(c, cat, T.pair_base, T.cap + 1);
     dfree(c, cat, T.trav_base, T.cap + 1);
+    dfree(c, cat, T.big_base, T.cap + 1);
     dfree(c, cat, T.wave_rec, T.max_A / 64 + 2);
     dfree(c, cat, T.wave_off, T.max_A / 64 + 2);
     dfree(c, cat, T.wave_w, T.max_A / 64 + 2);
@@ -382,7 +385,7 @@ spr_status graph_pass(spr_ctx *c, const Table &T, const PassGrids &g, hipGraph_t
 }
 
 // Profiling: add one recorded event set's kernel intervals to their slots.
-constexpr int PASS_SLOTS[PASS_KERNELS] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10};
+constexpr int PASS_SLOTS[PASS_KERNELS] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
 
 spr_status prof_collect(spr_ctx *c, spr_ctx::ProfRec &rec) {
     if (!rec.pending) return SPR_OK;
@@ -511,6 +514,7 @@ spr_status spr_ctx_destroy(spr_ctx *c) {
     dfree(c, MEM_SCRATCH, W.miss_list, oK); dfree(c, MEM_SCRATCH, W.miss_slot, oK);
     dfree(c, MEM_SCRATCH, W.pair_rank, oP); dfree(c, MEM_SCRATCH, W.s_ray, oP); dfree(c, MEM_SCRATCH, W.s_q, oP); dfree(c, MEM_SCRATCH, W.s_vi, oP);
     dfree(c, MEM_SCRATCH, W.vis_nsl, 8 * oP);
+    dfree(c, MEM_SCRATCH, W.seg_buf, (size_t)SEG_BIG_NS * SEG_BIG_LANES);
     size_t ns = c->cache.n_slots;
     dfree(c, MEM_CACHE, c->cache.slots, ns * 64);
     dfree(c, MEM_CACHE, c->cache.owner, ns);
@@ -612,8 +616,8 @@ spr_status spr_ctx_set_tuning(spr_ctx *c, const spr_tuning *t) {
     if (!c || !t) return fail(SPR_E_INVALID, "null argument");
     if (t->pairs_per_wg != 128 && t->pairs_per_wg != 256)
         return fail(SPR_E_INVALID, "pairs_per_wg must be 128 or 256 (got %u)", t->pairs_per_wg);
-    if (t->slot_tile != 16 && t->slot_tile != 32)
-        return fail(SPR_E_INVALID, "slot_tile must be 16 or 32 (got %u)", t->slot_tile);
+    if (t->slot_tile != 0 && t->slot_tile != 16 && t->slot_tile != 32)
+        return fail(SPR_E_INVALID, "slot_tile must be 0, 16 or 32 (got %u)", t->slot_tile);
     if (t->pairs_per_wg != c->rt_tile || t->slot_tile != c->rt_lb) {
         c->rt_tile = t->pairs_per_wg;
         c->rt_lb = t->slot_tile;
@@ -838,7 +842,6 @@ static void free_render_buffers(spr_ctx *c, spr_render *r) {
     dfree(c, MEM_RAYS, q.tslot, n);
     dfree(c, MEM_RAYS, q.best, n);
     dfree(c, MEM_RAYS, q.nfound, n);
-    dfree(c, MEM_RAYS, q.done_cnt, n);
     dfree(c, MEM_RAYS, q.def_first, n);
     dfree(c, MEM_RAYS, q.rbase, n);
     dfree(c, MEM_RAYS, q.rns, n);
@@ -886,7 +889,6 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
         if ((st = dalloc(c, MEM_RAYS, npix, &q.tslot)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.best)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.nfound)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.done_cnt)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.def_first)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.rbase)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_RAYS, npix, &q.rns)) != SPR_OK) break;
@@ -1075,6 +1077,7 @@ spr_status spr_render_get_info(spr_render *r, spr_render_info *o) {
     o->passes = s.passes;
     o->pairs = s.tot_pairs;
     o->bcmc_blocks = s.bcmc;
+    o->iso_coarse_cells = s.ccells;
     return SPR_OK;
 }
 

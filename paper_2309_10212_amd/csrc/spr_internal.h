@@ -109,6 +109,7 @@ struct ReqState {
     uint32_t pad[1];
     unsigned long long tot_pairs;
     unsigned long long bcmc;    // blocks whose fine range contains the isovalue (set up with the masks)
+    unsigned long long ccells;  // coarse cells whose range contains the isovalue (their fine ranges were read)
     unsigned long long wsum;    // sum of the active rays' weights for the next pass (per-ray counts)
 };
 
@@ -147,7 +148,6 @@ struct ReqDev {
     uint64_t *best;             // per pixel: minimum over this pass's hits of
                                 // pair slot << 38 | cell << 32 | rgba, ~0 for none
     uint32_t *nfound;           // per pixel: candidate blocks the traversal found this pass
-    uint32_t *done_cnt;         // per pixel: the ray's pairs finished this pass (0 between passes)
     uint32_t *def_first;        // per pixel: first deferred slot of the ray this pass (NONE between passes)
     uint32_t *rbase;            // per pixel: the ray's first pair slot this pass
     uint32_t *rns;              // per pixel: the ray's speculation count this pass
@@ -209,6 +209,9 @@ struct Table {
     uint32_t *act_base;         // cap+1, 64-aligned prefix of n_act
     uint32_t *pair_base;        // cap+1, prefix of n_act*n_spec
     uint32_t *trav_base;        // cap+1, 64-aligned prefix of n_act*segs (traversal lanes)
+    uint32_t *big_base;         // cap+1, prefix of n_act*segs over the requests whose segmented
+                                // lanes list more candidates than the LDS buffer holds (their
+                                // rows of Work::seg_buf)
     uint4 *wave_rec;            // per 64-entry wave of the A space, accumulated during a pass
                                 // and cleared by its compaction: {alive rays (initial-ray pass
                                 // only), pairs, deferred pairs, terminated rays}
@@ -219,6 +222,13 @@ struct Table {
     uint32_t max_A;             // capacity of the A space (sum of padded npix)
     uint32_t max_P;             // capacity of the pair space (sum of npix)
 };
+
+// Segmented traversal (several lanes per ray, for passes with few active
+// rays) of requests whose speculation count exceeds the lanes' LDS buffer:
+// at most SEG_BIG_LANES such lanes per pass, each listing at most
+// SEG_BIG_NS candidates.
+constexpr uint32_t SEG_BIG_LANES = 65536;
+constexpr uint32_t SEG_BIG_NS = 64;
 
 // Context-level scratch for one pass, sized for the largest table.
 struct Work {
@@ -231,6 +241,8 @@ struct Work {
     uint32_t *s_q;              // sorted pairs: pair slot within the request
     uint32_t *s_vi;             // sorted pairs: visible-list index
     uint32_t *vis_nsl;          // per visible block: slots of its 2x2x2 block neighbourhood (8, NONE outside)
+    uint32_t *seg_buf;          // SEG_BIG_NS x SEG_BIG_LANES: candidates of segmented traversal lanes
+                                // beyond the LDS buffer, entry k of lane l at [k * SEG_BIG_LANES + l]
     uint32_t cap_P;             // pairs capacity
     uint32_t cap_K;             // active/miss list capacity
 };

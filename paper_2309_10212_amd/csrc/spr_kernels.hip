@@ -269,12 +269,16 @@ __global__ __launch_bounds__(64) void k_pass_begin(PassCtl *ctl, Table T, int is
     for (uint32_t r = l + 64u; r < nreq; r += 64u) my += T.reqs[r].st->n_act;
     uint32_t all_na;
     (void)wave_incl_scan(my, &all_na);
-    uint32_t segs_all = 1;
+    uint32_t segs_all = 1, segs_big = 1;
     if (!is_init && all_na > 0) {
         const uint32_t want = SEG_TARGET / all_na;
         while (segs_all < 16u && 2u * segs_all <= want) segs_all *= 2u;
+        // requests whose lanes may list more candidates than the LDS buffer
+        // keep the excess in Work::seg_buf: all_na * segs_big <= SEG_BIG_LANES
+        const uint32_t want_big = SEG_BIG_LANES / all_na;
+        while (segs_big < 16u && 2u * segs_big <= want_big) segs_big *= 2u;
     }
-    uint32_t A = 0, P = 0, rays = 0, AT = 0;   // running bases, wave-uniform
+    uint32_t A = 0, P = 0, rays = 0, AT = 0, BL = 0;   // running bases, wave-uniform
     for (uint32_t r0 = 0; r0 < nreq; r0 += 64u) {
         const uint32_t r = r0 + l;
         const bool valid = r < nreq;
@@ -287,17 +291,21 @@ __global__ __launch_bounds__(64) void k_pass_begin(PassCtl *ctl, Table T, int is
         // per-ray counts: each ray's count is at most cap and they sum to at
         // most w*h, so the request's slot space is the smaller of the two
         const uint64_t pr_space = (uint64_t)na * cap < (uint64_t)npx ? (uint64_t)na * cap : (uint64_t)npx;
-        const bool seg_ok = pol == SPEC_PER_RAY ? cap <= TR_BUF : ns <= TR_BUF;
-        const uint32_t segs = (na > 0 && seg_ok) ? segs_all : 1u;
+        const uint32_t most = pol == SPEC_PER_RAY ? cap : ns;   // most candidates a ray lists
+        const bool seg_ok = most <= TR_BUF, big_ok = !seg_ok && most <= SEG_BIG_NS;
+        const uint32_t segs = na > 0 ? (seg_ok ? segs_all : (big_ok ? segs_big : 1u)) : 1u;
         const uint32_t a = round64(na), at = round64(na * segs);
+        const uint32_t bl = (big_ok && segs > 1u) ? na * segs : 0u;
         const uint32_t pp = is_init ? 0u : (pol == SPEC_PER_RAY ? (uint32_t)pr_space : na * ns);
-        uint32_t ta, tat, tp, tr;
+        uint32_t ta, tat, tp, tr, tb;
         const uint32_t ia = wave_incl_scan(a, &ta), iat = wave_incl_scan(at, &tat), ip = wave_incl_scan(pp, &tp);
+        const uint32_t ib = wave_incl_scan(bl, &tb);
         (void)wave_incl_scan(na, &tr);
         if (valid) {
             st->segs = segs;
             st->slot_cursor = pol == SPEC_PER_RAY ? 0u : pp;   // per-ray counts: handed out by the traversal
             T.trav_base[r] = AT + iat - at;
+            T.big_base[r] = BL + ib - bl;
             T.act_base[r] = A + ia - a;
             T.pair_base[r] = P + ip - pp;
             st->n_act_prev = na;
@@ -308,7 +316,7 @@ __global__ __launch_bounds__(64) void k_pass_begin(PassCtl *ctl, Table T, int is
                 st->passes = ps + 1u;
             }
         }
-        A += ta; P += tp; AT += tat; rays += tr;
+        A += ta; P += tp; AT += tat; rays += tr; BL += tb;
     }
     if (l != 0) return;
     ctl->pass += 1;
@@ -335,34 +343,77 @@ __global__ __launch_bounds__(64) void k_pass_begin(PassCtl *ctl, Table T, int is
 // The walk loads one word per coarse cell and tests blocks in registers.
 // The set bits also count the blocks whose fine range contains the isovalue
 // (one atomic per workgroup into the request's state).
+//
+// A wave takes 64 consecutive coarse cells: lane l tests the coarse range of
+// cell c0 + l; for the cells that pass (up to four at a time), lane i reads
+// the fine range of block i of the cell, and the ballot of the lanes' tests
+// is the cell's word.  Every fine range read is one of a cell whose coarse
+// range contains the isovalue, and the four cells' reads are in flight
+// together.  The kernel also seeds the empty-space distances: 0 for a
+// nonzero word, CD_MAX otherwise.
 __global__ __launch_bounds__(256) void k_iso_masks(Table T, const VolDev *vols) {
-    __shared__ unsigned long long s_cnt;
+    __shared__ unsigned long long s_cnt, s_cells;
     const ReqDev &q = T.reqs[0];
-    const VolDev &V = vols[q.vol];
-    const float iso = q.iso;
-    const uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
-    if (threadIdx.x == 0) s_cnt = 0;
+    const VolDev &V = vols[uni(q.vol)];
+    const float iso = uni(q.iso);
+    const uint32_t nc0 = (uint32_t)uni(V.nc[0]), nc1 = (uint32_t)uni(V.nc[1]), nc2 = (uint32_t)uni(V.nc[2]);
+    const int nb0 = uni(V.nb[0]), nb1 = uni(V.nb[1]), nb2 = uni(V.nb[2]);
+    const uint64_t nc = (uint64_t)nc0 * nc1 * nc2;
+    const float2 *__restrict__ coarse = uni(V.coarse);
+    const float2 *__restrict__ fine = uni(V.fine);
+    const gptr<uint64_t> out = as_global(uni(q.cmask64));
+    const gptr<uint8_t> occ = as_global(uni(q.cdist) + nc);
+    if (threadIdx.x == 0) { s_cnt = 0; s_cells = 0; }
     __syncthreads();
-    unsigned long long my = 0;
-    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nc; c += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t bits = 0;
-        float2 cr = V.coarse[c];
-        if (cr.x <= iso && iso <= cr.y) {
-            int cx, cy, cz;
-            unravel3((uint32_t)c, (uint32_t)V.nc[0], (uint32_t)V.nc[1], cx, cy, cz);
-            for (int i = 0; i < 64; ++i) {
-                int x = 4 * cx + (i & 3), y = 4 * cy + ((i >> 2) & 3), z = 4 * cz + (i >> 4);
-                if (x >= V.nb[0] || y >= V.nb[1] || z >= V.nb[2]) continue;
-                float2 r = V.fine[((uint64_t)z * V.nb[1] + y) * V.nb[0] + x];
-                bits |= (uint64_t)(r.x <= iso && iso <= r.y) << i;
+    const uint32_t lane = lane_id();
+    const int ox = (int)(lane & 3u), oy = (int)((lane >> 2) & 3u), oz = (int)(lane >> 4);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    unsigned long long my = 0, mycells = 0;
+    for (uint64_t c0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64; c0 < nc; c0 += nwaves * 64) {
+        const uint64_t c = c0 + lane;
+        bool cand = false;
+        if (c < nc) {
+            const float2 cr = coarse[c];
+            cand = cr.x <= iso && iso <= cr.y;
+        }
+        uint64_t todo = __ballot(cand);
+        mycells += lane == 0u ? (unsigned long long)__popcll(todo) : 0ull;
+        uint64_t mine = 0;
+        while (todo) {
+            int k[4];
+            float2 r[4];
+            bool in[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                k[u] = todo ? __ffsll((unsigned long long)todo) - 1 : -1;
+                todo &= todo ? todo - 1 : 0ull;
+                in[u] = false;
+                r[u] = make_float2(1.0f, 0.0f);
+                if (k[u] >= 0) {
+                    int cx, cy, cz;
+                    unravel3((uint32_t)(c0 + (uint64_t)k[u]), nc0, nc1, cx, cy, cz);
+                    const int x = 4 * cx + ox, y = 4 * cy + oy, z = 4 * cz + oz;
+                    in[u] = x < nb0 && y < nb1 && z < nb2;
+                    if (in[u]) r[u] = fine[((uint64_t)z * (uint32_t)nb1 + (uint32_t)y) * (uint32_t)nb0 + (uint32_t)x];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t bits = __ballot(in[u] && r[u].x <= iso && iso <= r[u].y);
+                if (k[u] >= 0 && (int)lane == k[u]) mine = bits;
             }
         }
-        q.cmask64[c] = bits;
-        my += (unsigned long long)__popcll(bits);
+        if (c < nc) {
+            out[c] = mine;
+            occ[c] = mine != 0ull ? (uint8_t)0 : (uint8_t)CD_MAX;   // input of the empty-space distances
+        }
+        my += (unsigned long long)__popcll(mine);
     }
     if (my) atomicAdd(&s_cnt, my);
+    if (mycells) atomicAdd(&s_cells, mycells);
     __syncthreads();
     if (threadIdx.x == 0 && s_cnt) atomicAdd(&q.st->bcmc, s_cnt);
+    if (threadIdx.x == 0 && s_cells) atomicAdd(&q.st->ccells, s_cells);
 }
 
 // Empty-space distances (per request, after the masks).  Chessboard distance
@@ -371,36 +422,65 @@ __global__ __launch_bounds__(256) void k_iso_masks(Table T, const VolDev *vols) 
 // along x, then y, then z gives, per cell, the distance (capped at CD_MAX) to
 // the nearest nonzero cell.  Capping only underestimates: the walk then jumps
 // less far, never over a nonzero cell.
-__global__ __launch_bounds__(256) void k_cdist_occ(Table T, const VolDev *vols) {
-    const ReqDev &q = T.reqs[0];
-    const VolDev &V = vols[q.vol];
-    const uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
-    uint8_t *occ = q.cdist + nc;
-    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nc; c += (uint64_t)gridDim.x * blockDim.x)
-        occ[c] = q.cmask64[c] != 0 ? 0 : (uint8_t)CD_MAX;
-}
 
-__global__ __launch_bounds__(256) void k_cdist_pass(Table T, const VolDev *vols, int axis) {
+// One separable pass along `axis`, tiled through LDS: a workgroup takes 32
+// positions along the axis (plus the CD_MAX positions on either side) of 64
+// adjacent lines, reads them once, and every output takes its 2*CD_MAX+1
+// window from LDS.  Positions outside the volume read as 255, which never
+// lowers a minimum.
+constexpr int CD_TA = 32, CD_TL = 64, CD_SPAN = CD_TA + 2 * CD_MAX;
+
+template <int AXIS>
+__global__ __launch_bounds__(256) void k_cdist_pass(Table T, const VolDev *vols) {
+    __shared__ uint8_t s_win[CD_SPAN][CD_TL];   // [position][line]
     const ReqDev &q = T.reqs[0];
-    const VolDev &V = vols[q.vol];
-    const uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    const VolDev &V = vols[uni(q.vol)];
+    const int n0 = uni(V.nc[0]), n1 = uni(V.nc[1]), n2 = uni(V.nc[2]);
+    const uint64_t nc = (uint64_t)n0 * n1 * n2;
+    uint8_t *const cd = uni(q.cdist);
     // x: scratch -> final, y: final -> scratch, z: scratch -> final
-    const uint8_t *src = (axis == 1) ? q.cdist : q.cdist + nc;
-    uint8_t *dst = (axis == 1) ? q.cdist + nc : q.cdist;
-    const int n_a = V.nc[axis];
-    const uint64_t stride = axis == 0 ? 1ull : (axis == 1 ? (uint64_t)V.nc[0] : (uint64_t)V.nc[0] * V.nc[1]);
-    for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nc; c += (uint64_t)gridDim.x * blockDim.x) {
-        const int p = (int)(((uint32_t)c / (uint32_t)stride) % (uint32_t)n_a);
-        int best = CD_MAX;
-        for (int k = -CD_MAX; k <= CD_MAX; ++k) {
-            const int pk = p + k;
-            if (pk < 0 || pk >= n_a) continue;
-            const int v = src[(int64_t)c + (int64_t)k * (int64_t)stride];
-            const int ak = k < 0 ? -k : k;
-            const int d = ak > v ? ak : v;
-            best = d < best ? d : best;
+    const uint8_t *src = AXIS == 1 ? cd : cd + nc;
+    uint8_t *dst = AXIS == 1 ? cd + nc : cd;
+    // the axis, the line axis (x, or y for the x pass) and the third axis
+    const int na = AXIS == 0 ? n0 : (AXIS == 1 ? n1 : n2);
+    const int nl = AXIS == 0 ? n1 : n0;
+    const int n3 = AXIS == 2 ? n1 : n2;
+    auto index = [&](int pa, int pl, int p3) -> uint64_t {
+        const int x = AXIS == 0 ? pa : pl;
+        const int y = AXIS == 0 ? pl : (AXIS == 1 ? pa : p3);
+        const int z = AXIS == 2 ? pa : p3;
+        return ((uint64_t)z * (uint32_t)n1 + (uint32_t)y) * (uint32_t)n0 + (uint32_t)x;
+    };
+    const int tiles_a = (na + CD_TA - 1) / CD_TA, tiles_l = (nl + CD_TL - 1) / CD_TL;
+    const int ntiles = tiles_a * tiles_l * n3;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int ta = tile % tiles_a, tl = (tile / tiles_a) % tiles_l, t3 = tile / (tiles_a * tiles_l);
+        const int a0 = ta * CD_TA - CD_MAX, l0 = tl * CD_TL;
+        for (int e = threadIdx.x; e < CD_SPAN * CD_TL; e += blockDim.x) {
+            // the x pass reads along x (contiguous), the others across lines along x
+            const int pos = AXIS == 0 ? e % CD_SPAN : e / CD_TL;
+            const int line = AXIS == 0 ? e / CD_SPAN : e % CD_TL;
+            const int pa = a0 + pos, pl = l0 + line;
+            uint8_t v = 255;
+            if (pa >= 0 && pa < na && pl < nl) v = src[index(pa, pl, t3)];
+            s_win[pos][line] = v;
         }
-        dst[c] = (uint8_t)best;
+        __syncthreads();
+        const int line = threadIdx.x % CD_TL, pl = l0 + line;
+        for (int pos = threadIdx.x / CD_TL; pos < CD_TA; pos += blockDim.x / CD_TL) {
+            const int pa = ta * CD_TA + pos;
+            if (pa >= na || pl >= nl) continue;
+            int best = CD_MAX;
+#pragma unroll
+            for (int k = -CD_MAX; k <= CD_MAX; ++k) {
+                const int v = s_win[pos + CD_MAX + k][line];
+                const int ak = k < 0 ? -k : k;
+                const int d = ak > v ? ak : v;
+                best = d < best ? d : best;
+            }
+            dst[index(pa, pl, t3)] = (uint8_t)best;
+        }
+        __syncthreads();
     }
 }
 
@@ -435,8 +515,7 @@ __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
             h.cell = NONE;
             q.hits[i] = h;
             q.act[1][i] = i;
-            q.best[i] = ~0ull;       // per-pixel pass state: no hit, no pair finished, nothing deferred
-            q.done_cnt[i] = 0u;
+            q.best[i] = ~0ull;       // per-pixel pass state: no hit, nothing deferred
             q.def_first[i] = NONE;
         }
         uint64_t m = __ballot(alive);
@@ -462,7 +541,7 @@ __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
 __device__ __forceinline__ bool range_has(float2 r, float iso) { return r.x <= iso && iso <= r.y; }
 
 
-__global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const VolDev *vols) {
+__global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const VolDev *vols, Work W) {
     __shared__ uint32_t s_slot[TR_BUF][256];
     const uint32_t AT = ctl->A_trav;
     const uint32_t nreq = ctl->nreq;
@@ -547,6 +626,12 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         const gptr<uint32_t> slots = as_global(uni(q.pair_blk) + (size_t)rbase_i);
         const gptr<uint32_t> pray = as_global(uni(q.pair_ray) + (size_t)rbase_i);
         const bool per_ray = pol == SPEC_PER_RAY;
+        // a segmented lane that may list more candidates than its LDS buffer
+        // moves each full buffer to its column of seg_buf (its request has
+        // rows there: big_base)
+        const bool big = L > 1u && nsr > TR_BUF;
+        const uint32_t bli = big ? uni(T.big_base[r]) + local : 0u;
+        const gptr<uint32_t> sbuf = as_global(W.seg_buf);
         // Segments (L > 1): the rest of the ray, [t_start, t_exit], is cut at
         // t_k = t_start + (t_exit - t_start) k / L; lane k lists the blocks whose
         // entry parameter lies in [t_k, t_k+1) (the first lane everything below
@@ -646,10 +731,16 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                     const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * u.nb[1] + cb[1]) * u.nb[0] + cb[0]);
                     s_slot[nbuf][threadIdx.x] = bid;
                     found++;
-                    if (++nbuf == TR_BUF && L == 1u) {   // segmented rays keep their count <= TR_BUF in LDS
-                        for (uint32_t k = 0; k < TR_BUF; ++k) {
-                            slots[flushed + k] = s_slot[k][threadIdx.x];
-                            if (per_ray) pray[flushed + k] = i;
+                    if (++nbuf == TR_BUF && (L == 1u || big)) {
+                        if (L == 1u) {
+                            for (uint32_t k = 0; k < TR_BUF; ++k) {
+                                slots[flushed + k] = s_slot[k][threadIdx.x];
+                                if (per_ray) pray[flushed + k] = i;
+                            }
+                        } else {
+                            gptr<uint32_t> d = sbuf + ((size_t)flushed * SEG_BIG_LANES + bli);
+#pragma unroll 1
+                            for (uint32_t k = 0; k < TR_BUF; ++k, d += SEG_BIG_LANES) *d = s_slot[k][threadIdx.x];
                         }
                         flushed += TR_BUF;
                         nbuf = 0;
@@ -692,7 +783,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
             const uint32_t total = (uint32_t)__shfl((int)incl, (int)(L - 1u), (int)L);
             for (uint32_t k = 0; k < found; ++k)
                 if (before + k < nsr) {
-                    slots[before + k] = s_slot[k][threadIdx.x];
+                    slots[before + k] = k < flushed ? sbuf[(size_t)k * SEG_BIG_LANES + bli] : s_slot[k - flushed][threadIdx.x];
                     if (per_ray) pray[before + k] = i;
                 }
             if (seg == 0u) {
@@ -1065,24 +1156,10 @@ __global__ __launch_bounds__(256) void k_assign_scatter(PassCtl *ctl, Table T, c
         const uint32_t pix = (cur ? act1 : act)[ii];
         if (vi >= vadm) {
             // a pair on a block not served this pass (cache-capacity rule):
-            // the ray keeps its progress up to its first such slot.  It counts
-            // as finished for the ray's pair count; when every pair of the
-            // ray is deferred, nothing is raytraced and the ray stays as it
-            // was, so the last of them resets the ray's pass state here.
-            uint32_t *const dfirst = q.def_first, *const dcnt = q.done_cnt;
-            const uint32_t nf = q.nfound[pix], rb = q.rbase[pix];
-            const uint32_t wave = (T.act_base[r] + ii) >> 6;
-            uint4 *const rec = T.wave_rec + wave;
-            atomicMin(dfirst + pix, qq - rb);
-            atomicAdd(&rec->z, 1u);
-            // acquire-release: the minimum above is visible to whichever pair
-            // finishes the ray, and that pair sees every other pair's
-            if (__hip_atomic_fetch_add(dcnt + pix, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == nf) {
-                dcnt[pix] = 0u;
-                dfirst[pix] = NONE;
-                // the ray stays where it was: same weight next pass
-                if (per_ray) atomicAdd(T.wave_w + wave, q.rw[pix]);
-            }
+            // the ray keeps its progress up to its first such slot (k_finish
+            // reads the minimum after the kernel boundary)
+            atomicMin(q.def_first + pix, qq - q.rbase[pix]);
+            atomicAdd(&T.wave_rec[(T.act_base[r] + ii) >> 6].z, 1u);
             continue;
         }
         const uint32_t dst = W.vis_off[vi] + rank;
@@ -1143,13 +1220,11 @@ __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols,
 }
 
 // ------------------------------------------------------- finishing a ray --
-// Depth composite and termination of one ray (Sec. 4.4), run by the last of
-// its pairs to finish (in the raytrace, or in the scatter when every pair of
-// the ray was deferred and there is nothing to finish).  The ray's slots
-// i*N_spec .. i*N_spec + nfound - 1 hold its candidate blocks in traversal
-// order.  best holds the minimum hit key of the ray's raytraced pairs, and
-// def_first the first slot whose block was not served this pass (NONE if
-// all were).
+// Depth composite and termination of one ray (Sec. 4.4), after the raytrace
+// of its pass.  The ray's slots rbase .. rbase + nfound - 1 hold its
+// candidate blocks in traversal order.  best holds the minimum hit key of the
+// ray's raytraced pairs, and def_first the first slot whose block was not
+// served this pass (NONE if all were).
 //   - a hit in a slot before def_first is the closest hit: image, hit buffer,
 //     the ray terminates;
 //   - otherwise, with a deferred slot, the ray keeps its progress up to the
@@ -1157,18 +1232,13 @@ __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols,
 //   - otherwise (every candidate served, no hit) the ray terminates if the
 //     walk found fewer than N_spec blocks (it left the volume), and else
 //     resumes after its last candidate.
-// The ray's per-pixel pass state is reset for the next pass.
-__device__ __forceinline__ void finish_ray(const Table &T, const VolDev *vols, uint32_t r, uint32_t pix, uint32_t qq) {
-    const ReqDev &q = T.reqs[r];
-    uint64_t *const bestp = q.best;
-    uint32_t *const ray_state = q.ray_state, *const pblk = q.pair_blk;
-    uint32_t *const dcnt = q.done_cnt, *const dfirst = q.def_first;
-    const bool per_ray = q.policy == SPEC_PER_RAY;
+// The ray's per-pixel pass state is reset for the next pass.  *w is the
+// survivor's weight for the next pass (per-ray counts).
+__device__ __forceinline__ bool finish_ray(const ReqDev &q, const VolDev *vols, uint32_t pix, uint32_t nf,
+                                           uint32_t &w) {
     const uint32_t base = q.rbase[pix], ns = q.rns[pix];
-    const uint32_t i = per_ray ? q.pair_ray[qq] : qq / ns;
-    const uint32_t nf = q.nfound[pix];
-    const uint64_t best = __hip_atomic_load(bestp + pix, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t d = __hip_atomic_load(dfirst + pix, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t best = q.best[pix];
+    const uint32_t d = q.def_first[pix];
     const uint32_t kb = best != ~0ull ? (uint32_t)(best >> 38) - base : NONE;
     bool term = false;
     uint32_t next = NONE;   // the block the ray resumes after, if it moved
@@ -1176,27 +1246,26 @@ __device__ __forceinline__ void finish_ray(const Table &T, const VolDev *vols, u
         q.image[pix] = (uint32_t)best;
         spr_hit h;
         h.t = q.tslot[base + kb];
-        h.block_id = pblk[base + kb];
+        h.block_id = q.pair_blk[base + kb];
         h.cell = (uint32_t)(best >> 32) & 63u;
         q.hits[pix] = h;
         term = true;
     } else if (d != NONE) {
-        if (d > 0u) next = pblk[base + d - 1u];
+        if (d > 0u) next = q.pair_blk[base + d - 1u];
     } else if (nf < ns) {
         term = true;
     } else {
-        next = pblk[base + nf - 1u];
+        next = q.pair_blk[base + nf - 1u];
     }
-    const uint32_t wave = (T.act_base[r] + i) >> 6;
+    w = 0;
     if (term) {
-        ray_state[pix] = RAY_DONE;
-        atomicAdd(&T.wave_rec[wave].w, 1u);
+        q.ray_state[pix] = RAY_DONE;
     } else {
-        if (next != NONE) ray_state[pix] = next;
-        if (per_ray) {
+        if (next != NONE) q.ray_state[pix] = next;
+        if (q.policy == SPEC_PER_RAY) {
             // the survivor's weight for the next pass: from where it leaves
             // the block it resumes after (the traversal's restart point)
-            uint32_t w = q.rw[pix];
+            w = q.rw[pix];
             if (next != NONE) {
                 const VolDev &V = vols[q.vol];
                 Ray R;
@@ -1208,21 +1277,65 @@ __device__ __forceinline__ void finish_ray(const Table &T, const VolDev *vols, u
                 walk_init(R, LB, cb, wb);
                 w = ray_weight(walk_exit(wb), R.tx);
             }
-            atomicAdd(T.wave_w + wave, w);
         }
     }
-    if (best != ~0ull) bestp[pix] = ~0ull;
-    dcnt[pix] = 0u;
-    if (d != NONE) dfirst[pix] = NONE;
+    if (best != ~0ull) q.best[pix] = ~0ull;
+    if (d != NONE) q.def_first[pix] = NONE;
+    return term;
+}
+
+// K10: every active ray with candidates this pass is finished (finish_ray);
+// the rays the traversal found no candidate for were terminated by it.  One
+// thread per entry of the active-ray space, whose waves are the wave records'
+// waves (64-aligned per request): a wave adds its terminations and its
+// survivors' weights to its own record (no other kernel writes them now).
+__global__ __launch_bounds__(256) void k_finish(PassCtl *ctl, Table T, const VolDev *vols) {
+    const uint32_t A = ctl->A;
+    const uint32_t nreq = ctl->nreq;
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
+        const uint32_t r = uni(find_req(T.act_base, nreq, p));
+        const ReqDev &q = T.reqs[r];
+        const ReqState *st = uni(q.st);
+        const uint32_t i = p - uni(T.act_base[r]);
+        bool term = false;
+        uint32_t w = 0;
+        if (i < uni(st->n_act_prev)) {
+            const uint32_t pix = uni(q.act[uni(st->cur)])[i];
+            const uint32_t nf = q.nfound[pix];
+            if (nf > 0u) term = finish_ray(q, vols, pix, nf, w);
+        }
+        const uint32_t nt = (uint32_t)__popcll(__ballot(term));
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) w += (uint32_t)__shfl_xor((int)w, off);
+        if (lane_id() == 0) {
+            if (nt) T.wave_rec[p >> 6].w += nt;
+            if (w) T.wave_w[p >> 6] += w;
+        }
+    }
+}
+
+// A served pair's result: with a hit, the atomic minimum of its key into the
+// pixel's best word.  A ray's pair slots are consecutive and follow its
+// traversal, so the pair slot orders the ray's hits as t does (ties go to the
+// earlier block): the ray's first hit in slot order is the minimum of
+// slot << 38 | cell << 32 | rgba over its hits (slots < 2^24).  t goes to the
+// pair's slot, where the minimum's slot finds it (the second step of the
+// resolve, in k_finish after the kernel boundary).
+__device__ __forceinline__ void pair_done(const ReqDev &q, uint32_t pix, uint32_t qq, uint32_t cell, uint32_t rgba,
+                                          double t) {
+    if (cell == NONE) return;
+    const uint64_t key = ((uint64_t)qq << 38) | ((uint64_t)cell << 32) | rgba;
+    q.tslot[qq] = t;
+    __hip_atomic_fetch_min(as_global(q.best) + pix, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------- K9 ------
 // Block raytrace (Sec. 3.7, 4.3): each served pair walks its ray through the
 // dual cells of its block (Amanatides-Woo restricted to the block) and tests
 // each cell (corner pretest, cubic, Marmitt isolation).  A pair whose ray hits
-// takes the atomic minimum of its key into the pixel's best word and writes
-// its hit record (t, cell, colour) at its pair slot; a pair without a hit
-// writes nothing.
+// takes the atomic minimum of its key (slot, cell, colour) into the pixel's
+// best word and writes its t at its pair slot; a pair without a hit writes
+// nothing.
 __device__ __forceinline__ float slot_value(const float *slots, const uint32_t ns[8], int lx, int ly, int lz) {
     int nb = (lx >> 2) | ((ly >> 2) << 1) | ((lz >> 2) << 2);
     uint32_t s = ns[nb];
@@ -1374,26 +1487,100 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
                 t0 = tx;
             }
             if (guard == 16) atomicAdd(&ctl->guard, 1u);
-            if (out.cell != NONE) {
-                // A ray's pair slots are consecutive and follow its traversal,
-                // so the pair slot orders the ray's hits as t does (ties go to
-                // the earlier block): the ray's first hit in slot order is the
-                // minimum of slot << 38 | cell << 32 | rgba over its hits
-                // (slots < 2^24).  t goes to the pair's slot, where the
-                // minimum's slot finds it (the second step of the resolve).
-                const uint64_t key = ((uint64_t)qq << 38) | ((uint64_t)out.cell << 32) | out.rgba;
-                q.tslot[qq] = out.t;
-                __hip_atomic_fetch_min(as_global(q.best) + pix, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            // The pair is done.  The ray's pairs count themselves off
-            // (acquire-release, so the hits above are visible to the last);
-            // the last of them finishes the ray: depth composite, termination
-            // and its traversal state for the next pass.
-            const uint32_t nf = q.nfound[pix];
-            if (__hip_atomic_fetch_add(q.done_cnt + pix, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u == nf)
-                finish_ray(T, vols, r, pix, qq);
+            pair_done(q, pix, qq, out.cell, out.rgba, out.t);
         }
         __syncthreads();   // the next tile reuses the LDS
+    }
+}
+
+// The 8 corner values of dual cell (lx, ly, lz) of a block (local cell
+// coordinates 0..3) straight from the cache slots of its 2x2x2 block
+// neighbourhood: corner offset o (bit 0 x, 1 y, 2 z) lies in neighbour
+// o & h, h the axes on which the cell is the block's last (its + corners are
+// the neighbour's first samples).  All eight loads are issued together.
+__device__ __forceinline__ void load_corners(const float *__restrict__ slots, const uint32_t nsl[8], int lx, int ly,
+                                             int lz, float fc[8]) {
+    const uint32_t h = (lx == 3 ? 1u : 0u) | (ly == 3 ? 2u : 0u) | (lz == 3 ? 4u : 0u);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t o = (uint32_t)k & h;
+        uint32_t s = nsl[0];
+        // nsl[o] with o a subset of k's bits: a short select chain per corner
+#pragma unroll
+        for (int m = 1; m < 8; ++m)
+            if ((m & ~k) == 0) s = o == (uint32_t)m ? nsl[m] : s;
+        const int x = (lx + (k & 1)) & 3, y = (ly + ((k >> 1) & 1)) & 3, z = (lz + (k >> 2)) & 3;
+        fc[k] = s != NONE ? slots[(size_t)s * 64 + (uint32_t)(x + 4 * y + 16 * z)] : 0.0f;
+    }
+}
+
+// Block raytrace without LDS staging: one served pair per lane.  When a
+// block carries one or two pairs (the common case once speculation spreads
+// the rays' slots over many blocks), staging its 125-value dual grid costs
+// more loads than the pair's own corner reads (eight per cell, issued
+// together; adjacent cells share a face, so the second read mostly hits the
+// cache).  Same walk, cell test, shading and composite as the staged kernel.
+// The camera and volume fields are read per lane: in a batch, the pairs of
+// one block come from every request that sees it.
+__global__ __launch_bounds__(256, 3) void k_raytrace_direct(PassCtl *ctl, Table T, const VolDev *vols, Work W,
+                                                             Cache C) {
+    const uint32_t n = ctl->served;
+    const float *__restrict__ slots = C.slots;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const uint32_t vi = W.s_vi[j];
+        const uint32_t ray = W.s_ray[j];
+        const uint32_t qq = W.s_q[j];
+        const uint32_t r = ray >> 24, pix = ray & 0xFFFFFFu;
+        const uint4 n0 = reinterpret_cast<const uint4 *>(W.vis_nsl + (size_t)vi * 8)[0];
+        const uint4 n1 = reinterpret_cast<const uint4 *>(W.vis_nsl + (size_t)vi * 8)[1];
+        const uint32_t nsl[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+        const uint32_t b = (uint32_t)W.vis_list[vi];
+        const ReqDev &q = T.reqs[r];
+        const VolDev &V = vols[q.vol];
+        const float iso = q.iso;
+        int bb[3];
+        bb[0] = (int)(b % (uint32_t)V.nb[0]);
+        bb[1] = (int)((b / (uint32_t)V.nb[0]) % (uint32_t)V.nb[1]);
+        bb[2] = (int)(b / ((uint32_t)V.nb[0] * (uint32_t)V.nb[1]));
+        Ray R;
+        make_ray(q, V.n, pix, R);
+        const Level LB = {4, {V.tb[0], V.tb[1], V.tb[2]}, {V.n[0], V.n[1], V.n[2]}, 0.25};
+        const Level L1 = {1, {V.n[0] - 1, V.n[1] - 1, V.n[2] - 1}, {V.n[0], V.n[1], V.n[2]}, 1.0};
+        int lo[3], hi[3], c[3];
+        const double tb0 = cell_entry(R, LB, bb);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = 4 * bb[a];
+            hi[a] = 4 * bb[a] + 3;
+            if (hi[a] > V.n[a] - 2) hi[a] = V.n[a] - 2;
+            c[a] = cell_at(R, L1, a, tb0, lo[a], hi[a]);
+        }
+        // entry parameter: cell_entry for the first cell; afterwards the
+        // previous cell's exit (the stepped axes' entry planes are the old
+        // exit planes, every other entry plane lies before them)
+        double t0 = cell_entry(R, L1, c);
+        float fc[8];
+        load_corners(slots, nsl, c[0] - lo[0], c[1] - lo[1], c[2] - lo[2], fc);
+        double out_t = __builtin_inf();
+        uint32_t out_cell = NONE, out_rgba = 0u;
+        int guard = 0;
+        for (; guard < 16; ++guard) {   // at most 10 cells of a 4^3 block lie on a ray
+            const double tx = cell_exit(R, L1, c);
+            const double t1 = tx < R.tx ? tx : R.tx;
+            CellHit h;
+            test_cell(R, c, t0, t1, fc, iso, h);
+            if (h.hit) {
+                out_t = t0 + h.s;
+                out_cell = (uint32_t)((c[0] - lo[0]) + 4 * (c[1] - lo[1]) + 16 * (c[2] - lo[2]));
+                out_rgba = shade_hit(R, h, fc);
+                break;
+            }
+            if (tx > R.tx || !advance(R, L1, c, tx, lo, hi)) break;
+            load_corners(slots, nsl, c[0] - lo[0], c[1] - lo[1], c[2] - lo[2], fc);
+            t0 = tx;
+        }
+        if (guard == 16) atomicAdd(&ctl->guard, 1u);
+        pair_done(q, pix, qq, out_cell, out_rgba, out_t);
     }
 }
 
@@ -1698,10 +1885,10 @@ hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const V
         ++k;
     };
     mark();   // masks, then the empty-space distances (timed together)
-    hipLaunchKernelGGL(k_iso_masks, dim3(grid_for(mask_words, 256, 1024)), dim3(256), 0, s, T, vols);
-    hipLaunchKernelGGL(k_cdist_occ, dim3(grid_for(mask_words, 256, 4096)), dim3(256), 0, s, T, vols);
-    for (int a = 0; a < 3; ++a)
-        hipLaunchKernelGGL(k_cdist_pass, dim3(grid_for(mask_words, 256, 4096)), dim3(256), 0, s, T, vols, a);
+    hipLaunchKernelGGL(k_iso_masks, dim3(grid_for(mask_words, 256, 4096)), dim3(256), 0, s, T, vols);
+    hipLaunchKernelGGL(k_cdist_pass<0>, dim3(grid_for(mask_words, CD_TA * CD_TL, 4096)), dim3(256), 0, s, T, vols);
+    hipLaunchKernelGGL(k_cdist_pass<1>, dim3(grid_for(mask_words, CD_TA * CD_TL, 4096)), dim3(256), 0, s, T, vols);
+    hipLaunchKernelGGL(k_cdist_pass<2>, dim3(grid_for(mask_words, CD_TA * CD_TL, 4096)), dim3(256), 0, s, T, vols);
     mark(); hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, ctl, T, 1);
     mark(); hipLaunchKernelGGL(k_init_rays, dim3(grid_for(T.max_A, 256, 16384)), dim3(256), 0, s, ctl, T, vols);
     mark(); hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, s, ctl, T, 1);
@@ -1712,11 +1899,11 @@ hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const V
 
 const char *const PASS_KERNEL_NAMES[PASS_KERNELS] = {
     "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_evict_hist", "k_evict",
-    "k_assign_scatter", "k_decode", "k_raytrace", "k_pass_end", "k_compact"};
+    "k_assign_scatter", "k_decode", "k_raytrace", "k_finish", "k_pass_end", "k_compact"};
 
 const char *const PROF_NAMES[PROF_SLOTS] = {
     "k_pass_begin", "k_traverse", "k_dedupe", "k_mark", "k_evict_hist", "k_evict",
-    "k_assign_scatter", "k_decode", "k_raytrace", "k_pass_end", "k_compact",
+    "k_assign_scatter", "k_decode", "k_raytrace", "k_finish", "k_pass_end", "k_compact",
     "k_block_ranges", "k_fine_grid", "k_coarse_grid", "k_iso_masks", "k_init_rays"};
 
 hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, const Work &W,
@@ -1727,7 +1914,7 @@ hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev
         ++k;
     };
     mark(); hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, ctl, T, 0);
-    mark(); hipLaunchKernelGGL(k_traverse, dim3(g.rays), dim3(256), 0, s, ctl, T, vols);
+    mark(); hipLaunchKernelGGL(k_traverse, dim3(g.rays), dim3(256), 0, s, ctl, T, vols, W);
     mark(); hipLaunchKernelGGL(k_dedupe, dim3(g.dedupe), dim3(256), 0, s, ctl, T, vols, W);
     mark(); hipLaunchKernelGGL(k_mark, dim3(g.pairs), dim3(256), 0, s, ctl, vols, W, C);
     mark(); hipLaunchKernelGGL(k_evict_hist, dim3(g.slots), dim3(256), 0, s, ctl, C);
@@ -1735,10 +1922,12 @@ hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev
     mark(); hipLaunchKernelGGL(k_assign_scatter, dim3(g.assign + g.scatter), dim3(256), 0, s, ctl, T, vols, W, C, g.assign);
     mark(); hipLaunchKernelGGL(k_decode, dim3(g.decode), dim3(64), 0, s, ctl, vols, W, C);
     mark();
-    if (g.rt_tile == 128 && g.rt_lb == 16) hipLaunchKernelGGL((k_raytrace<128, 16>), dim3(g.rt), dim3(128), 0, s, ctl, T, vols, W, C);
+    if (g.rt_lb == 0) hipLaunchKernelGGL(k_raytrace_direct, dim3(g.rt), dim3(256), 0, s, ctl, T, vols, W, C);
+    else if (g.rt_tile == 128 && g.rt_lb == 16) hipLaunchKernelGGL((k_raytrace<128, 16>), dim3(g.rt), dim3(128), 0, s, ctl, T, vols, W, C);
     else if (g.rt_tile == 128) hipLaunchKernelGGL((k_raytrace<128, 32>), dim3(g.rt), dim3(128), 0, s, ctl, T, vols, W, C);
     else if (g.rt_lb == 16) hipLaunchKernelGGL((k_raytrace<256, 16>), dim3(g.rt), dim3(256), 0, s, ctl, T, vols, W, C);
     else hipLaunchKernelGGL((k_raytrace<256, 32>), dim3(g.rt), dim3(256), 0, s, ctl, T, vols, W, C);
+    mark(); hipLaunchKernelGGL(k_finish, dim3(g.rays), dim3(256), 0, s, ctl, T, vols);
     mark(); hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, s, ctl, T, 0);
     mark(); hipLaunchKernelGGL(k_compact, dim3(g.rays), dim3(256), 0, s, ctl, T);
     if (ev) (void)hipEventRecord(ev[k], s);

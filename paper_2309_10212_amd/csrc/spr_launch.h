@@ -18,7 +18,7 @@ struct PassGrids {
     uint32_t decode;    // 64-thread groups decoding misses (one thread per block)
     uint32_t rt;        // raytrace workgroups
     uint32_t rt_tile;   // sorted pairs per raytrace workgroup: 128 or 256
-    uint32_t rt_lb;     // blocks staged in LDS per raytrace tile: 16 or 32
+    uint32_t rt_lb;     // blocks staged in LDS per raytrace tile: 16 or 32, 0 = no staging
     uint64_t max_P;     // pair capacity the shape was made for
 };
 
@@ -38,14 +38,15 @@ hipError_t launch_release_volume(hipStream_t s, PassCtl *ctl, const Cache &C, ui
 // path, with ev[5] after the last kernel.
 hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words,
                             hipEvent_t *ev = nullptr);
-constexpr int PASS_KERNELS = 11;
+constexpr int PASS_KERNELS = 12;
 extern const char *const PASS_KERNEL_NAMES[PASS_KERNELS];
 // Profiling slots: the pass kernels, then the load-path and set-up kernels
 // that run outside a pass.
 constexpr int PROF_SLOTS = PASS_KERNELS + 5;
 extern const char *const PROF_NAMES[PROF_SLOTS];
-constexpr int LOAD_SLOTS[3] = {11, 12, 13};           // block ranges, fine grid, coarse grid
-constexpr int INIT_SLOTS[5] = {14, 0, 15, 9, 10};     // masks, pass begin, initial rays, pass end, compact
+constexpr int LOAD_SLOTS[3] = {PASS_KERNELS, PASS_KERNELS + 1, PASS_KERNELS + 2};   // block ranges, fine grid, coarse grid
+// masks, pass begin, initial rays, pass end, compact
+constexpr int INIT_SLOTS[5] = {PASS_KERNELS + 3, 0, PASS_KERNELS + 4, PASS_KERNELS - 2, PASS_KERNELS - 1};
 // ev == nullptr: plain launches; else ev[i] is recorded before kernel i and
 // ev[PASS_KERNELS] after the last one.
 hipError_t launch_pass(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, const Work &W,

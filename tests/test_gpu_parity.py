@@ -16,10 +16,13 @@ pytestmark = pytest.mark.gpu
 T_TOL = 1e-4
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[(256, 32), (256, 0)], ids=["staged", "direct"])
+def ctx(request):
+    """A context with each block-raytrace variant: dual grids staged in LDS
+    per tile, or every pair reading its corners from the cache slots."""
     from paper_2309_10212_amd import spr
     c = spr.Context(device=0, cache_bytes=256 << 20)
+    c.set_tuning(*request.param)
     yield c
     c.close()
 
@@ -158,8 +161,10 @@ def test_tiny_render_and_pass_counters(ctx, cap):
         for k in ("n_active", "n_spec", "pairs", "visible", "active_blocks", "terminated"):
             assert g[k] == o[k], (p, k, g, o)
     # the BCMC-proxy count: blocks whose fine range contains the isovalue
-    _, fine, _ = oracle.grids(dec)
+    _, fine, coarse = oracle.grids(dec)
     assert r.info()["bcmc_blocks"] == oracle.blocks_containing(fine, iso)
+    # the coarse cells whose range contains the isovalue (their fine ranges are read for the masks)
+    assert r.info()["iso_coarse_cells"] == oracle.blocks_containing(coarse, iso)
     r.free()
     vol.free()
 
