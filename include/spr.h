@@ -138,6 +138,8 @@ typedef struct {
     uint64_t walk_guard;      /* ray walks (traversal or block raytrace) ended by a step guard instead of
                                  by leaving the domain, the block, or finding their blocks; every step
                                  advances a cell index, so this is 0 unless the walk logic is broken */
+    uint64_t coarse_steps;    /* coarse cells the traversal visited (Sec. 3.3): one macrocell word (the
+                                 isovalue mask and the empty-space distance) read per visit */
 } spr_counters;
 
 /* Per-render summary. */

@@ -156,6 +156,8 @@ struct spr_render {
     hipGraphExec_t exec = nullptr;
     uint64_t graph_gen = ~0ull;
     uint64_t cwords = 0;   // isovalue mask size (one u64 per coarse cell)
+    void *buf = nullptr;   // every device buffer of the render, carved from one allocation
+    size_t buf_bytes = 0;
 };
 
 struct spr_batch {
@@ -170,6 +172,8 @@ struct spr_batch {
     uint4 *d_state = nullptr;   // cap + 1 gathered member records (k_gather_state)
     uint4 *h_state = nullptr;   // pinned copy
     bool state_fresh = false;   // h_state reflects the last pass and the current members
+    void *buf = nullptr;        // table, member descriptions and gathered records, one allocation
+    size_t buf_bytes = 0;
 };
 
 namespace {
@@ -228,6 +232,33 @@ void dfree(spr_ctx *c, MemCat cat, T *&p, size_t count) {
     dev_free(c, cat, (void *)p, count * sizeof(T));
     p = nullptr;
 }
+
+// Several arrays carved from one device allocation (each at a 256-byte
+// boundary): a render's buffers take one allocator call instead of twenty.
+struct Carve {
+    struct Item {
+        void **ptr;
+        size_t bytes;
+    };
+    std::vector<Item> items;
+    template <typename T>
+    void add(T **p, size_t count) { items.push_back({(void **)p, count * sizeof(T)}); }
+    size_t total() const {
+        size_t t = 0;
+        for (const Item &i : items) t += (i.bytes + 255) & ~(size_t)255;
+        return t;
+    }
+    spr_status alloc(spr_ctx *c, MemCat cat, void **base, size_t *bytes) {
+        *bytes = total();
+        CHK(dev_alloc(c, cat, *bytes, base));
+        char *p = (char *)*base;
+        for (const Item &i : items) {
+            *i.ptr = p;
+            p += (i.bytes + 255) & ~(size_t)255;
+        }
+        return SPR_OK;
+    }
+};
 
 // --------------------------------------------------------- camera basis ----
 // Pinhole basis in fp64 (the per-pixel part runs on the device):
@@ -312,34 +343,28 @@ spr_status ensure_work(spr_ctx *c, uint64_t P) {
     return SPR_OK;
 }
 
-spr_status alloc_table(spr_ctx *c, MemCat cat, uint32_t cap, uint64_t max_A, uint64_t max_P, Table &T) {
+// The arrays of a launch table, added to a carve.
+void carve_table(Carve &cv, uint32_t cap, uint64_t max_A, uint64_t max_P, Table &T) {
     T.cap = cap;
     T.max_A = (uint32_t)max_A;
     T.max_P = (uint32_t)max_P;
-    CHK(dalloc(c, cat, 1, &T.hdr));
-    CHK(dalloc(c, cat, cap + 1, &T.act_base));
-    CHK(dalloc(c, cat, cap + 1, &T.pair_base));
-    CHK(dalloc(c, cat, cap + 1, &T.trav_base));
-    CHK(dalloc(c, cat, cap + 1, &T.big_base));
-    CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_rec));
-    CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_off));
-    CHK(dalloc(c, cat, max_A / 64 + 2, &T.wave_w));
-    // wave records and weights accumulate during a pass and are cleared by
-    // its compaction: they start at zero
-    HIPCHK(launch_fill_u32(c->stream, reinterpret_cast<uint32_t *>(T.wave_rec), 4 * (max_A / 64 + 2), 0u));
-    HIPCHK(launch_fill_u32(c->stream, T.wave_w, max_A / 64 + 2, 0u));
-    return SPR_OK;
+    cv.add(&T.hdr, 1);
+    cv.add(&T.act_base, cap + 1);
+    cv.add(&T.pair_base, cap + 1);
+    cv.add(&T.trav_base, cap + 1);
+    cv.add(&T.big_base, cap + 1);
+    cv.add(&T.wave_rec, max_A / 64 + 2);
+    cv.add(&T.wave_off, max_A / 64 + 2);
+    cv.add(&T.wave_w, max_A / 64 + 2);
 }
 
-void free_table(spr_ctx *c, MemCat cat, Table &T) {
-    dfree(c, cat, T.hdr, 1);
-    dfree(c, cat, T.act_base, T.cap + 1);
-    dfree(c, cat, T.pair_base, T.cap + 1);
-    dfree(c, cat, T.trav_base, T.cap + 1);
-    dfree(c, cat, T.big_base, T.cap + 1);
-    dfree(c, cat, T.wave_rec, T.max_A / 64 + 2);
-    dfree(c, cat, T.wave_off, T.max_A / 64 + 2);
-    dfree(c, cat, T.wave_w, T.max_A / 64 + 2);
+// Wave records and weights accumulate during a pass and are cleared by its
+// compaction: they start at zero.  (A render's own table needs no clearing:
+// its initial-ray pass writes every record it uses.)
+spr_status clear_table_records(spr_ctx *c, const Table &T) {
+    HIPCHK(launch_fill_u32(c->stream, reinterpret_cast<uint32_t *>(T.wave_rec), 4 * ((uint64_t)T.max_A / 64 + 2), 0u));
+    HIPCHK(launch_fill_u32(c->stream, T.wave_w, (uint64_t)T.max_A / 64 + 2, 0u));
+    return SPR_OK;
 }
 
 spr_status set_table_count(spr_ctx *c, Table &T, uint32_t n) {
@@ -578,6 +603,7 @@ spr_status spr_ctx_counters(spr_ctx *c, spr_counters *o) {
     o->served_pairs = p.acc_served;
     o->max_active_blocks = p.acc_max_active;
     o->walk_guard = p.acc_guard;
+    o->coarse_steps = p.acc_csteps;
     return SPR_OK;
 }
 
@@ -833,27 +859,9 @@ spr_status spr_debug_fp64_ops(spr_ctx *c, const double *x, const double *y, size
 // ----------------------------------------------------------------- render --
 
 static void free_render_buffers(spr_ctx *c, spr_render *r) {
-    uint32_t n = r->npix;
-    ReqDev &q = r->hreq;
-    dfree(c, MEM_RAYS, q.ray_state, n);
-    dfree(c, MEM_RAYS, q.act[0], n);
-    dfree(c, MEM_RAYS, q.act[1], n);
-    dfree(c, MEM_RAYS, q.pair_blk, n);
-    dfree(c, MEM_RAYS, q.tslot, n);
-    dfree(c, MEM_RAYS, q.best, n);
-    dfree(c, MEM_RAYS, q.nfound, n);
-    dfree(c, MEM_RAYS, q.def_first, n);
-    dfree(c, MEM_RAYS, q.rbase, n);
-    dfree(c, MEM_RAYS, q.rns, n);
-    dfree(c, MEM_RAYS, q.rw, n);
-    dfree(c, MEM_RAYS, q.pair_ray, n);
-    dfree(c, MEM_RAYS, q.image, n);
-    dfree(c, MEM_RAYS, q.hits, n);
-    dfree(c, MEM_RAYS, r->d_st, 1);
-    dfree(c, MEM_RAYS, r->d_req, 1);
-    dfree(c, MEM_RAYS, q.cmask64, r->cwords);
-    dfree(c, MEM_RAYS, q.cdist, 2 * r->cwords);
-    free_table(c, MEM_RAYS, r->table);
+    dev_free(c, MEM_RAYS, r->buf, r->buf_bytes);
+    r->buf = nullptr;
+    r->buf_bytes = 0;
 }
 
 spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uint32_t w, uint32_t h,
@@ -880,33 +888,32 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     q.vol = v->idx;
     q.spec_cap = c->spec_cap;
     HIPCHK(hipSetDevice(c->device));
-    spr_status st = SPR_OK;
-    do {
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.ray_state)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.act[0])) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.act[1])) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.pair_blk)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.tslot)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.best)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.nfound)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.def_first)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.rbase)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.rns)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.rw)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.pair_ray)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.image)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, npix, &q.hits)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, 1, &r->d_st)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, 1, &r->d_req)) != SPR_OK) break;
-        {
-            const VolDev &V = c->h_vols[v->idx];
-            r->cwords = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
-        }
-        if ((st = dalloc(c, MEM_RAYS, r->cwords, &q.cmask64)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_RAYS, 2 * r->cwords, &q.cdist)) != SPR_OK) break;
-        if ((st = alloc_table(c, MEM_RAYS, 1, round64h(npix), npix, r->table)) != SPR_OK) break;
-        st = ensure_work(c, npix);
-    } while (0);
+    {
+        const VolDev &V = c->h_vols[v->idx];
+        r->cwords = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
+    }
+    Carve cv;
+    cv.add(&q.ray_state, npix);
+    cv.add(&q.act[0], npix);
+    cv.add(&q.act[1], npix);
+    cv.add(&q.pair_blk, npix);
+    cv.add(&q.tslot, npix);
+    cv.add(&q.best, npix);
+    cv.add(&q.nfound, npix);
+    cv.add(&q.def_first, npix);
+    cv.add(&q.rbase, npix);
+    cv.add(&q.rns, npix);
+    cv.add(&q.rw, npix);
+    cv.add(&q.pair_ray, npix);
+    cv.add(&q.image, npix);
+    cv.add(&q.hits, npix);
+    cv.add(&r->d_st, 1);
+    cv.add(&r->d_req, 1);
+    cv.add(&q.cmask64, r->cwords);
+    cv.add(&q.cdist, 2 * r->cwords);
+    carve_table(cv, 1, round64h(npix), npix, r->table);
+    spr_status st = cv.alloc(c, MEM_RAYS, &r->buf, &r->buf_bytes);
+    if (st == SPR_OK) st = ensure_work(c, npix);
     if (st != SPR_OK) {
         free_render_buffers(c, r);
         delete r;
@@ -918,10 +925,9 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     ReqState s0{};
     s0.n_act = (uint32_t)npix;
     s0.cur = 1;
-    const uint32_t one = 1;
-    hipError_t e = hipMemcpy(r->d_st, &s0, sizeof(s0), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(r->table.hdr, &one, sizeof(one), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(r->d_req, &q, sizeof(q), hipMemcpyHostToDevice);
+    // description, initial state and request count written in stream order
+    // (kernel arguments: no host synchronisation)
+    hipError_t e = launch_put_req(c->stream, r->d_req, q, r->d_st, &s0, r->table.hdr, 1u);
     hipEvent_t *pev = nullptr;
     if (e == hipSuccess && c->prof && prof_begin(c, 5, INIT_SLOTS, &pev) != SPR_OK) e = hipErrorUnknown;
     if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols, r->cwords, pev);
@@ -943,17 +949,10 @@ spr_status spr_render_set_spec_cap(spr_render *r, uint32_t cap) {
     if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
     spr_ctx *c = r->ctx;
     HIPCHK(hipSetDevice(c->device));
-    ReqState s;
-    CHK(read_state(c, r->d_st, &s));
+    // the first pass takes its count from the cap in the description
+    // (k_pass_begin), so only the description changes
     r->hreq.spec_cap = cap;
-    if (s.n_act > 0) {
-        uint32_t ns = r->npix / s.n_act;
-        if (ns < 1) ns = 1;
-        if (ns > cap) ns = cap;
-        s.n_spec = ns;
-    }
-    HIPCHK(hipMemcpy(r->d_st, &s, sizeof(s), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(r->d_req, &r->hreq, sizeof(ReqDev), hipMemcpyHostToDevice));
+    HIPCHK(launch_put_req(c->stream, r->d_req, r->hreq, nullptr, nullptr, nullptr, 0u));
     return SPR_OK;
 }
 
@@ -965,9 +964,8 @@ spr_status spr_render_set_spec_policy(spr_render *r, uint32_t policy) {
     if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
     spr_ctx *c = r->ctx;
     HIPCHK(hipSetDevice(c->device));
-    HIPCHK(hipStreamSynchronize(c->stream));
     r->hreq.policy = policy;
-    HIPCHK(hipMemcpy(r->d_req, &r->hreq, sizeof(ReqDev), hipMemcpyHostToDevice));
+    HIPCHK(launch_put_req(c->stream, r->d_req, r->hreq, nullptr, nullptr, nullptr, 0u));
     return SPR_OK;
 }
 
@@ -1074,6 +1072,11 @@ spr_status spr_render_get_info(spr_render *r, spr_render_info *o) {
     o->rays_entered = s.passes ? s.entered : s.n_act;
     o->n_active = s.n_act;
     o->n_spec = s.n_spec;
+    if (s.passes == 0 && s.n_act > 0) {
+        // before the first pass the count follows the current cap (as k_pass_begin takes it)
+        uint32_t ns = r->npix / s.n_act;
+        o->n_spec = ns < 1u ? 1u : (ns > r->hreq.spec_cap ? r->hreq.spec_cap : ns);
+    }
     o->passes = s.passes;
     o->pairs = s.tot_pairs;
     o->bcmc_blocks = s.bcmc;
@@ -1136,9 +1139,12 @@ spr_status spr_batch_create_empty(spr_ctx *c, uint32_t max_requests, uint64_t ma
     if (!b) return fail(SPR_E_OOM, "host allocation failed");
     b->ctx = c;
     b->max_pixels = max_pixels;
-    spr_status st = alloc_table(c, MEM_SCRATCH, max_requests, A, P, b->table);
-    if (st == SPR_OK) st = dalloc(c, MEM_SCRATCH, max_requests, &b->table.reqs);
-    if (st == SPR_OK) st = dalloc(c, MEM_SCRATCH, (size_t)max_requests + 1, &b->d_state);
+    Carve cv;
+    carve_table(cv, max_requests, A, P, b->table);
+    cv.add(&b->table.reqs, max_requests);
+    cv.add(&b->d_state, (size_t)max_requests + 1);
+    spr_status st = cv.alloc(c, MEM_SCRATCH, &b->buf, &b->buf_bytes);
+    if (st == SPR_OK) st = clear_table_records(c, b->table);
     if (st == SPR_OK && hipHostMalloc((void **)&b->h_state, sizeof(uint4) * ((size_t)max_requests + 1),
                                       hipHostMallocDefault) != hipSuccess) {
         b->h_state = nullptr;
@@ -1147,9 +1153,7 @@ spr_status spr_batch_create_empty(spr_ctx *c, uint32_t max_requests, uint64_t ma
     if (st == SPR_OK) st = ensure_work(c, P);
     if (st == SPR_OK) st = set_table_count(c, b->table, 0);
     if (st != SPR_OK) {
-        free_table(c, MEM_SCRATCH, b->table);
-        dfree(c, MEM_SCRATCH, b->table.reqs, max_requests);
-        dfree(c, MEM_SCRATCH, b->d_state, (size_t)max_requests + 1);
+        dev_free(c, MEM_SCRATCH, b->buf, b->buf_bytes);
         if (b->h_state) (void)hipHostFree(b->h_state);
         delete b;
         return st;
@@ -1286,9 +1290,8 @@ spr_status spr_batch_free(spr_batch *b) {
     HIPCHK(hipStreamSynchronize(c->stream));
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    free_table(c, MEM_SCRATCH, b->table);
-    dfree(c, MEM_SCRATCH, b->table.reqs, b->table.cap);
-    dfree(c, MEM_SCRATCH, b->d_state, (size_t)b->table.cap + 1);
+    dev_free(c, MEM_SCRATCH, b->buf, b->buf_bytes);
+    b->buf = nullptr;
     if (b->h_state) (void)hipHostFree(b->h_state);
     for (auto *r : b->renders) r->batch = nullptr;
     delete b;

@@ -284,10 +284,17 @@ __global__ __launch_bounds__(64) void k_pass_begin(PassCtl *ctl, Table T, int is
         const bool valid = r < nreq;
         ReqState *st = r0 == 0 ? st0 : (valid ? T.reqs[r].st : nullptr);
         const uint32_t na = r0 == 0 ? na0 : (valid ? st->n_act : 0u);
-        const uint32_t ns = r0 == 0 ? ns0 : (valid ? st->n_spec : 0u);
+        const uint32_t ns_in = r0 == 0 ? ns0 : (valid ? st->n_spec : 0u);
         const uint32_t ps = r0 == 0 ? ps0 : (valid ? st->passes : 0u);
         const uint32_t pol = valid ? T.reqs[r].policy : SPEC_UNIFORM;
         const uint32_t cap = valid ? T.reqs[r].spec_cap : 0u, npx = valid ? T.reqs[r].npix : 0u;
+        // a request's first pass takes N_spec = clamp(floor(w*h / N_act), 1, cap) (Sec. 4) with its
+        // current cap (the cap may change between the initial rays and the first pass)
+        uint32_t ns = ns_in;
+        if (!is_init && ps == 0u && na > 0u) {
+            const uint32_t q0 = npx / na;
+            ns = q0 < 1u ? 1u : (q0 > cap ? cap : q0);
+        }
         // per-ray counts: each ray's count is at most cap and they sum to at
         // most w*h, so the request's slot space is the smaller of the two
         const uint64_t pr_space = (uint64_t)na * cap < (uint64_t)npx ? (uint64_t)na * cap : (uint64_t)npx;
@@ -324,6 +331,7 @@ __global__ __launch_bounds__(64) void k_pass_begin(PassCtl *ctl, Table T, int is
     ctl->cursor = 0; ctl->served = 0; ctl->deferred = 0; ctl->need = 0; ctl->evict_T = 64;
     ctl->evict_done_blocks = 0; ctl->evicted = 0; ctl->terminated = 0; ctl->pairs = 0; ctl->overflow = 0;
     ctl->guard = 0;
+    ctl->csteps = 0;
     ctl->rays = rays;
     T.act_base[nreq] = A;
     T.pair_base[nreq] = P;
@@ -665,8 +673,10 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         // jump or a coarse step.  Inner loop: the blocks of a nonempty coarse
         // cell, no memory access but the LDS staging.
         bool guard_hit = false;
+        uint32_t csteps = 0;   // coarse cells visited (mask word and distance loaded)
         while (alive && found < nsr) {
             if (++steps > max_steps) { alive = false; guard_hit = true; break; }   // every step advances an index
+            ++csteps;
             if (tcur >= t_hi && !fresh) { seg_done = true; break; }   // the rest is the next lane's
             const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
             const uint64_t cm = cmask[cid];
@@ -813,11 +823,16 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         for (int bit = 0; bit < 13; ++bit)   // found <= ns <= 4096: a sum of bit planes over the lanes
             wpairs += (uint32_t)__popcll(__ballot(lead && ((found >> bit) & 1u))) << bit;
         const uint32_t wterm = (uint32_t)__popcll(__ballot(term));
+        uint32_t wsteps = 0;
+#pragma unroll
+        for (int bit = 0; bit < 16; ++bit)   // csteps <= max_steps < 2^16
+            wsteps += (uint32_t)__popcll(__ballot((csteps >> bit) & 1u)) << bit;
         const uint64_t act = __ballot(1);
         if ((int)lane_id() == __ffsll((unsigned long long)act) - 1) {
             uint4 *rec = T.wave_rec + ((uni(T.act_base[r]) + i) >> 6);
             if (wpairs) atomicAdd(&rec->y, wpairs);
             if (wterm) atomicAdd(&rec->w, wterm);
+            if (wsteps) atomicAdd(&ctl->csteps, wsteps);
         }
     }
 }
@@ -1623,14 +1638,12 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
     const uint32_t w0 = t * per < nw ? t * per : nw;
     const uint32_t w1 = w0 + per < nw ? w0 + per : nw;
     uint32_t run = 0;
-    // up to PE_REG records per thread are loaded once, all at the start, and
-    // kept in registers (unrolled, so their indices are compile-time)
-    constexpr uint32_t PE_REG = 8;
+    // up to PE_REG records per thread are read in two halves of PE_REG / 2,
+    // each half's loads issued together, and their survivor counts kept in
+    // registers for the offsets (unrolled, so the indices are compile-time;
+    // 16 covers a 720p request's 14,400 waves)
+    constexpr uint32_t PE_REG = 16, PE_HALF = PE_REG / 2;
     const bool in_regs = per <= PE_REG;
-    uint4 rv[PE_REG];
-#pragma unroll
-    for (uint32_t k = 0; k < PE_REG; ++k)
-        rv[k] = (in_regs && w0 + k < w1) ? T.wave_rec[w0 + k] : make_uint4(0u, 0u, 0u, 0u);
     uint32_t surv[PE_REG] = {};
     if (w0 < w1) {
         uint32_t r = find_req(T.act_base, nreq, w0 << 6);
@@ -1665,8 +1678,15 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
         };
         if (in_regs) {
 #pragma unroll
-            for (uint32_t k = 0; k < PE_REG; ++k)
-                surv[k] = (w0 + k < w1) ? add(w0 + k, rv[k]) : 0u;
+            for (uint32_t h = 0; h < PE_REG; h += PE_HALF) {
+                uint4 rv[PE_HALF];
+#pragma unroll
+                for (uint32_t k = 0; k < PE_HALF; ++k)
+                    rv[k] = (w0 + h + k < w1) ? T.wave_rec[w0 + h + k] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+                for (uint32_t k = 0; k < PE_HALF; ++k)
+                    surv[h + k] = (w0 + h + k < w1) ? add(w0 + h + k, rv[k]) : 0u;
+            }
         } else {
             for (uint32_t w = w0; w < w1; ++w) (void)add(w, T.wave_rec[w]);
         }
@@ -1737,6 +1757,7 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
             ctl->acc_served += ctl->served;
             if (ctl->n_actblk > ctl->acc_max_active) ctl->acc_max_active = ctl->n_actblk;
             ctl->acc_guard += ctl->guard;
+            ctl->acc_csteps += ctl->csteps;
         }
     }
     for (uint32_t r = t; r < nreq; r += PE_THREADS) {
@@ -1794,6 +1815,15 @@ __global__ __launch_bounds__(256) void k_compact(PassCtl *ctl, Table T) {
 // Progress of the members of a launch table, for the host's scheduler: per
 // request {active rays, passes run, pairs of the last pass, N_spec}, then
 // {active blocks of the last pass, pass stamp, 0, 0}.  One workgroup.
+// Set-up writes in stream order, from kernel arguments: a request's
+// description, optionally its state and a launch table's request count.
+__global__ void k_put_req(ReqDev *dq, ReqDev q, ReqState *ds, ReqState st, uint32_t *hdr, uint32_t hv) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    *dq = q;
+    if (ds) *ds = st;
+    if (hdr) *hdr = hv;
+}
+
 __global__ void k_gather_state(const PassCtl *ctl, Table T, uint32_t n, uint4 *out) {
     for (uint32_t r = threadIdx.x; r < n; r += blockDim.x) {
         const ReqState *st = T.reqs[r].st;
@@ -1849,6 +1879,13 @@ hipError_t launch_load_grids(hipStream_t s, const VolDev &V, hipEvent_t *ev) {
     uint64_t nc = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
     mark(); hipLaunchKernelGGL(k_coarse_grid, dim3(grid_for(nc, 256, 1u << 16)), dim3(256), 0, s, V);
     mark();
+    return hipGetLastError();
+}
+
+hipError_t launch_put_req(hipStream_t s, ReqDev *dq, const ReqDev &q, ReqState *ds, const ReqState *st,
+                          uint32_t *hdr, uint32_t hv) {
+    const ReqState zero{};
+    hipLaunchKernelGGL(k_put_req, dim3(1), dim3(64), 0, s, dq, q, ds, st ? *st : zero, hdr, hv);
     return hipGetLastError();
 }
 

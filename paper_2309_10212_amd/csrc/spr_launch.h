@@ -29,6 +29,9 @@ hipError_t launch_fp64_ops(hipStream_t s, const double *x, const double *y, uint
 hipError_t launch_load_grids(hipStream_t s, const VolDev &V, hipEvent_t *ev = nullptr);
 // Members' progress of a table into out[0..n] (see k_gather_state).
 hipError_t launch_gather_state(hipStream_t s, const PassCtl *ctl, const Table &T, uint32_t n, uint4 *out);
+// Stream-ordered set-up writes: *dq = q; if ds, *ds = *st (zero if st is null); if hdr, *hdr = hv.
+hipError_t launch_put_req(hipStream_t s, ReqDev *dq, const ReqDev &q, ReqState *ds, const ReqState *st,
+                          uint32_t *hdr, uint32_t hv);
 hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t v);
 hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n, uint64_t v);
 hipError_t launch_iota_u32(hipStream_t s, uint32_t *p, uint64_t n);
