@@ -672,7 +672,7 @@ static void free_volume_buffers(spr_ctx *c, VolDev &V, size_t stream_bytes) {
     dfree(c, MEM_GRIDS, V.map, ns);
     dfree(c, MEM_GRIDS, V.blk_cnt, ns);
     dfree(c, MEM_GRIDS, V.vis_idx, ns);
-    dfree(c, MEM_GRIDS, V.act_stamp, ns);
+    dfree(c, MEM_GRIDS, V.claim, nc);
 }
 
 spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, const spr_volume_desc *d,
@@ -719,7 +719,7 @@ spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, co
         if ((st = dalloc(c, MEM_GRIDS, bidx_count(V), &V.map)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_GRIDS, bidx_count(V), &V.blk_cnt)) != SPR_OK) break;
         if ((st = dalloc(c, MEM_GRIDS, bidx_count(V), &V.vis_idx)) != SPR_OK) break;
-        if ((st = dalloc(c, MEM_GRIDS, bidx_count(V), &V.act_stamp)) != SPR_OK) break;
+        if ((st = dalloc(c, MEM_GRIDS, nc, &V.claim)) != SPR_OK) break;
     } while (0);
     if (st != SPR_OK) {
         free_volume_buffers(c, V, bytes);
@@ -729,7 +729,7 @@ spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, co
     if (e == hipSuccess) e = launch_fill_u32(c->stream, V.map, bidx_count(V), NONE);
     if (e == hipSuccess) e = launch_fill_u32(c->stream, V.blk_cnt, bidx_count(V), 0);
     if (e == hipSuccess) e = launch_fill_u32(c->stream, V.vis_idx, bidx_count(V), 0);
-    if (e == hipSuccess) e = launch_fill_u32(c->stream, V.act_stamp, bidx_count(V), 0);
+    if (e == hipSuccess) e = launch_fill_u64(c->stream, V.claim, nc, 0ull);
     if (e == hipSuccess) e = launch_load_grids(c->stream, V);
     c->h_vols[idx] = V;
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_vols + idx, &c->h_vols[idx], sizeof(VolDev), hipMemcpyHostToDevice, c->stream);

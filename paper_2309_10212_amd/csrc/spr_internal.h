@@ -31,7 +31,8 @@ struct VolDev {
     uint32_t *map;              // per block: cache slot or NONE
     uint32_t *blk_cnt;          // per block: pairs on it in the current pass (0 between passes)
     uint32_t *vis_idx;          // per block: index in that pass's visible list
-    uint32_t *act_stamp;        // per block: last pass it was active
+    uint64_t *claim;            // per coarse cell: bit (bx&3) + 4(by&3) + 16(bz&3) set once that block
+                                // was claimed active in the current pass (0 between passes)
     int n[3];                   // samples per axis
     int nb[3];                  // blocks per axis, ceil(n/4)
     int nc[3];                  // coarse cells per axis, ceil(nb/4)
@@ -45,7 +46,7 @@ struct VolDev {
 };
 
 // Index of block (bx, by, bz) in the per-block state arrays (map, blk_cnt,
-// vis_idx, act_stamp): the 64 blocks of a coarse cell are contiguous, at
+// vis_idx): the 64 blocks of a coarse cell are contiguous, at
 // (bx&3) + 4(by&3) + 16(bz&3) (the order of the isovalue mask bits), and the
 // coarse cells follow in raster order, so a block's +x/+y/+z neighbourhood
 // mostly lies in the same 256 bytes.  Block ids everywhere else are linear,
@@ -68,13 +69,14 @@ __device__ __forceinline__ uint32_t bidx(const VolDev &V, uint32_t b) {
 // the store changed them), which puts several dependent round trips to memory
 // in front of every access.
 struct VolState {
-    uint32_t *map, *blk_cnt, *vis_idx, *act_stamp;
+    uint32_t *map, *blk_cnt, *vis_idx;
+    uint64_t *claim;
     int nb0, nb1, nb2, nc0, nc1;
 };
 
 __device__ __forceinline__ VolState vol_state(const VolDev &V) {
     VolState s;
-    s.map = V.map; s.blk_cnt = V.blk_cnt; s.vis_idx = V.vis_idx; s.act_stamp = V.act_stamp;
+    s.map = V.map; s.blk_cnt = V.blk_cnt; s.vis_idx = V.vis_idx; s.claim = V.claim;
     s.nb0 = V.nb[0]; s.nb1 = V.nb[1]; s.nb2 = V.nb[2]; s.nc0 = V.nc[0]; s.nc1 = V.nc[1];
     return s;
 }

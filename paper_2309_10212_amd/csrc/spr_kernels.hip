@@ -936,7 +936,7 @@ __global__ __launch_bounds__(256) void k_dedupe(PassCtl *ctl, Table T, const Vol
 // (Sec. 3.4 cache-capacity rule) gets its run of sorted pairs (O_BRays of
 // Sec. 3.6) by block-aggregated bump allocation, and marks itself and its
 // +x/+y/+z face, edge and corner neighbours active (Sec. 3.4).  The first
-// visitor of a block this pass (per-block pass stamp) also does its cache
+// visitor of a block this pass (its bit in the coarse cell's claim word) also does its cache
 // lookup (Sec. 3.5): a hit refreshes the slot's LRU stamp, a miss is
 // appended to the miss list.  Pairs on blocks beyond the admitted prefix
 // are counted as deferred.
@@ -974,16 +974,20 @@ __global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, 
             cnt = bc[bi];
             bc[bi] = 0u;
             if (j < vadm) {
-                // The 8 neighbours in two straight-line steps - claims
-                // (exchange of the pass stamp), then slot map reads - so that
-                // each step's accesses go out together: one round trip per
-                // step, not per neighbour.  A neighbour outside the volume
-                // takes the block's own index (exchanged just before by
-                // neighbour 0, so it returns this pass) and is masked out.
-                const gptr<uint32_t> stamp = as_global(S.act_stamp);
+                // The 8 neighbours in two straight-line steps - claims, then
+                // slot map reads - so that each step's accesses go out
+                // together: one round trip per step, not per neighbour.  A
+                // claim sets the neighbour's bit in its coarse cell's claim
+                // word; the neighbours in one coarse cell (all 8 when the
+                // block is not on its cell's +x/+y/+z faces) are claimed by
+                // one atomic OR, and a neighbour whose bit was clear before
+                // is first.  A neighbour outside the volume takes the
+                // block's own index and is masked out.
+                const gptr<uint64_t> claim = as_global(S.claim);
                 const gptr<const uint32_t> map = as_global((const uint32_t *)S.map);
-                uint32_t nbi[8], ex[8], sl[8];
-                uint32_t inside = 0;
+                uint32_t nbi[8], sl[8];
+                uint64_t grp[8], old[8];
+                uint32_t inside = 0, lead = 0;
 #pragma unroll
                 for (int o = 0; o < 8; ++o) {
                     const int x2 = bx + (o & 1), y2 = by + ((o >> 1) & 1), z2 = bz + (o >> 2);
@@ -991,14 +995,34 @@ __global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, 
                     nbi[o] = ok ? bidx_xyz(S, x2, y2, z2) : bi;
                     inside |= ok ? 1u << o : 0u;
                 }
+                // brick index = coarse cell * 64 + bit: group the neighbours by cell
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    grp[o] = 0ull;
+                    bool first = true;
+#pragma unroll
+                    for (int o2 = 0; o2 < 8; ++o2) {
+                        const bool same = (nbi[o2] >> 6) == (nbi[o] >> 6);
+                        grp[o] |= same ? 1ull << (nbi[o2] & 63u) : 0ull;
+                        if (o2 < o && same) first = false;
+                    }
+                    lead |= first ? 1u << o : 0u;
+                }
 #pragma unroll
                 for (int o = 0; o < 8; ++o)
-                    ex[o] = __hip_atomic_exchange(stamp + nbi[o], pass, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    old[o] = ((lead >> o) & 1u) ? __hip_atomic_fetch_or(claim + (nbi[o] >> 6), grp[o], __ATOMIC_RELAXED,
+                                                                        __HIP_MEMORY_SCOPE_AGENT)
+                                                : 0ull;
 #pragma unroll
                 for (int o = 0; o < 8; ++o) sl[o] = map[nbi[o]];
 #pragma unroll
                 for (int o = 0; o < 8; ++o) {
-                    if (((inside >> o) & 1u) && ex[o] != pass) {   // first visitor this pass: cache lookup
+                    // the claim word's previous value, from the atomic of o's group
+                    uint64_t was = 0ull;
+#pragma unroll
+                    for (int o2 = 0; o2 < 8; ++o2)
+                        was |= ((nbi[o2] >> 6) == (nbi[o] >> 6)) ? old[o2] : 0ull;
+                    if (((inside >> o) & 1u) && !((was >> (nbi[o] & 63u)) & 1ull)) {   // first visitor: cache lookup
                         my_act++;
                         if (sl[o] == NONE) {
                             missmask |= 1u << o;
@@ -1226,6 +1250,17 @@ __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols,
         for (int o = 0; o < 8; ++o) nsl[o] = map[nbi[o]];
 #pragma unroll
         for (int o = 0; o < 8; ++o) nsl[o] = ((inside >> o) & 1u) ? nsl[o] : NONE;
+        // the marking's claims are done: clear the claim words this block's
+        // neighbourhood set (every claimed block is in the neighbourhood of an
+        // admitted visible block), so they are 0 for the next pass
+        const gptr<uint64_t> claim = as_global(V.claim);
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            bool first = true;
+#pragma unroll
+            for (int o2 = 0; o2 < o; ++o2) first = first && (nbi[o2] >> 6) != (nbi[o] >> 6);
+            if (first) claim[nbi[o] >> 6] = 0ull;
+        }
         uint4 *dst = reinterpret_cast<uint4 *>(W.vis_nsl + (size_t)v * 8);
         dst[0] = make_uint4(nsl[0], nsl[1], nsl[2], nsl[3]);
         dst[1] = make_uint4(nsl[4], nsl[5], nsl[6], nsl[7]);

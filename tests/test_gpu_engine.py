@@ -60,8 +60,9 @@ def test_memory_by_kind_returns_to_zero_and_allocations_balance():
     m1 = ctx.mem_split()
     assert m1["current"]["compressed"] >= s.nbytes
     nb = 16 ** 3
-    # per-block state: fine ranges (8 B) plus map, pair counter, visible index, stamp (4 B each)
-    assert nb * 24 <= m1["current"]["grids"] <= nb * 24 + 64 * 1024
+    # per-block state: fine ranges (8 B) plus map, pair counter, visible index (4 B each); per
+    # coarse cell of 4^3 blocks its range (8 B) and claim word (8 B)
+    assert nb * 20 + (nb // 64) * 16 <= m1["current"]["grids"] <= nb * 20 + 64 * 1024
     cam = volgen.orbit_camera(*dims, seed=1)
     rs = [spr.Render(vol, cam, 0.5, 96, 64, spec_cap=c) for c in (1, 16)]
     rs[0].run()
