@@ -74,7 +74,7 @@ typedef struct {
 } spr_config;
 
 /* A compressed volume (Sec. 3 overview: fixed-rate block compression).
- * nx, ny, nz >= 2 samples; rate_bits in 1..16 (coded) or 32 (raw float32);
+ * 2 <= nx, ny, nz <= SPR_MAX_EXTENT samples; rate_bits in 1..16 (coded) or 32 (raw float32);
  * src_dtype records what the samples were before conversion to float32;
  * codec_version must be SPR_CODEC_VERSION.  The stream holds
  * ceil(nx/4)*ceil(ny/4)*ceil(nz/4) records of 8*rate_bits bytes, block
@@ -88,7 +88,11 @@ typedef struct {
 
 /* Pinhole camera (Sec. 3.2): eye, look-at point, up vector, vertical field
  * of view in degrees.  Coordinates are in sample units: sample (i,j,k) sits
- * at the point (i,j,k). */
+ * at the point (i,j,k); each eye coordinate lies within +-SPR_MAX_EXTENT
+ * (render creation fails with SPR_E_INVALID otherwise).  With the volume
+ * extent limit this keeps every ray position below 2^20 blocks, where the
+ * traversal's fp32 block estimate is exact to a quarter block. */
+#define SPR_MAX_EXTENT 524288u
 typedef struct {
     double eye[3], center[3], up[3];
     double vfov_deg;

@@ -285,6 +285,8 @@ bool make_basis(const spr_camera *c, uint32_t w, uint32_t h, ReqDev &q) {
     for (int a = 0; a < 3; ++a) q.eye[a] = c->eye[a];
     for (int a = 0; a < 3; ++a)
         if (!isfinite(q.eye[a]) || !isfinite(q.fwd[a]) || !isfinite(q.right[a])) return false;
+    for (int a = 0; a < 3; ++a)
+        if (!(fabs(q.eye[a]) <= (double)SPR_MAX_EXTENT)) return false;
     return isfinite(th) && th > 0;
 }
 
@@ -681,6 +683,8 @@ spr_status spr_volume_load(spr_ctx *c, const void *host_stream, size_t bytes, co
     *out = nullptr;
     if (d->codec_version != SPR_CODEC_VERSION) return fail(SPR_E_INVALID, "unknown codec version %u", d->codec_version);
     if (d->nx < 2 || d->ny < 2 || d->nz < 2) return fail(SPR_E_INVALID, "volume must have at least 2 samples per axis");
+    if (d->nx > SPR_MAX_EXTENT || d->ny > SPR_MAX_EXTENT || d->nz > SPR_MAX_EXTENT)
+        return fail(SPR_E_INVALID, "volume extent above SPR_MAX_EXTENT samples on an axis");
     if (!((d->rate_bits >= 1 && d->rate_bits <= 16) || d->rate_bits == 32))
         return fail(SPR_E_INVALID, "rate_bits %u not in 1..16 or 32", d->rate_bits);
     if (d->src_dtype != SPR_DTYPE_F32 && d->src_dtype != SPR_DTYPE_U8) return fail(SPR_E_INVALID, "bad src_dtype");
@@ -881,7 +885,7 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     ReqDev &q = r->hreq;
     if (!make_basis(cam, w, h, q)) {
         delete r;
-        return fail(SPR_E_INVALID, "degenerate camera (zero view direction or view along up)");
+        return fail(SPR_E_INVALID, "degenerate camera (zero view direction, view along up, or eye beyond SPR_MAX_EXTENT)");
     }
     q.iso = iso;
     q.w = w; q.h = h; q.npix = (uint32_t)npix;

@@ -452,21 +452,22 @@ __device__ __forceinline__ int still_cell(const Ray &R, const Level &lv, int a) 
     return m / lv.S;
 }
 
-// cell index on axis a at parameter t, searched in [lo, hi] starting from a guess
+// Cell index on axis a at parameter t, within [lo, hi]: d > 0, the largest m
+// whose lower plane has tau <= t; d < 0, the smallest m whose upper plane
+// has tau <= t (clamped to [lo, hi] when no such m lies there).  The fp64
+// position estimate floor((o + t d) / S) is that cell or a neighbour: the
+// plane tests only differ from the position order within rounding of a
+// plane, and ray positions stay below 2^22 samples (volume extent and eye
+// coordinates are at most 2^19).  So the tests of the estimate's two planes
+// decide it.
 __device__ inline int cell_at(const Ray &R, const Level &lv, int a, double t, int lo, int hi) {
     if (R.d[a] == 0.0) return still_cell(R, lv, a);
     double p = R.o[a] + t * R.d[a];
     int g = (int)floor(p * lv.invS);   // == floor(p / S): S is a power of two
-
-    if (g < lo) g = lo;
-    if (g > hi) g = hi;
-    if (R.d[a] > 0.0) {
-        while (g < hi && tau_plane(R, lv, a, g + 1) <= t) ++g;
-        while (g > lo && tau_plane(R, lv, a, g) > t) --g;
-    } else {
-        while (g > lo && tau_plane(R, lv, a, g) <= t) --g;
-        while (g < hi && tau_plane(R, lv, a, g + 1) > t) ++g;
-    }
+    g = g < lo ? lo : (g > hi ? hi : g);
+    const bool lo_x = tau_plane(R, lv, a, g) <= t, hi_x = tau_plane(R, lv, a, g + 1) <= t;
+    if (R.d[a] > 0.0) g += (g < hi && hi_x) ? 1 : ((g > lo && !lo_x) ? -1 : 0);
+    else g += (g > lo && lo_x) ? -1 : ((g < hi && !hi_x) ? 1 : 0);
     return g;
 }
 
@@ -524,44 +525,42 @@ __device__ __forceinline__ double walk_exit(const AxisWalk &w) {
 
 // Cross every plane with parameter <= tn (tied planes together); false when
 // the ray leaves [lo, hi] on some axis.  The same cell and result as
-// advance(): each axis moves independently of the others, and a second round
-// only runs when two consecutive planes of an axis round to parameters <= tn.
+// advance().  One crossing per axis suffices: the next plane of an axis is at
+// least one sample further on and |r_a| >= 1 (|d_a| <= 1), so its parameter
+// exceeds tn by about |r_a| or more.
 __device__ __forceinline__ bool walk_step(const Ray &R, const Level &lv, AxisWalk &w, int c[3], double tn,
                                           const int lo[3], const int hi[3]) {
     bool ok = true;
-    for (int round = 0; round < 8; ++round) {
-        bool again = false;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const bool st = w.tex[a] <= tn;
-            c[a] += st ? axis_dir(R, a) : 0;
-            ok = ok && !(st && (c[a] < lo[a] || c[a] > hi[a]));
-            w.tex[a] = st ? exit_tau(R, lv, a, c[a]) : w.tex[a];
-            again = again || (st && w.tex[a] <= tn);
-        }
-        if (!again || !ok) break;
+    for (int a = 0; a < 3; ++a) {
+        const bool st = w.tex[a] <= tn;
+        c[a] += st ? axis_dir(R, a) : 0;
+        ok = ok && !(st && (c[a] < lo[a] || c[a] > hi[a]));
+        w.tex[a] = st ? exit_tau(R, lv, a, c[a]) : w.tex[a];
     }
     return ok;
 }
 
-// Cross every plane with tau <= tn.  Returns false when the ray leaves
-// [lo, hi] on some axis (for the full range: leaves the domain).
+// Cross every plane with tau <= tn (one per axis at most, as in walk_step).
+// Returns false when the ray leaves [lo, hi] on some axis (for the full
+// range: leaves the domain).
 __device__ inline bool advance(const Ray &R, const Level &lv, int c[3], double tn, const int lo[3], const int hi[3]) {
+    bool ok = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (R.d[a] > 0.0) {
-            while (tau_plane(R, lv, a, c[a] + 1) <= tn) {
+            if (tau_plane(R, lv, a, c[a] + 1) <= tn) {
                 ++c[a];
-                if (c[a] > hi[a]) return false;
+                ok = ok && c[a] <= hi[a];
             }
         } else if (R.d[a] < 0.0) {
-            while (tau_plane(R, lv, a, c[a]) <= tn) {
+            if (tau_plane(R, lv, a, c[a]) <= tn) {
                 --c[a];
-                if (c[a] < lo[a]) return false;
+                ok = ok && c[a] >= lo[a];
             }
         }
     }
-    return true;
+    return ok;
 }
 
 // ------------------------------------------------------------ cell test --

@@ -501,6 +501,24 @@ __device__ __forceinline__ uint32_t local_bit(const int cb[3]) {
 // that miss are terminated; image and hit buffer are cleared, and so is the
 // per-pixel pass state.  The alive counts feed the same count/compact kernels
 // as a pass.
+//
+// The active-ray list starts in tile order: initial index i covers the
+// pixels in 8x8 tiles (one wave each), tiles left to right within bands of 8
+// rows, bands top to bottom; the last band and each band's last tile may be
+// smaller.  Compaction keeps the order, so the rays of a wave stay close on
+// screen in every pass and walk similar cells: a wave lasts as long as its
+// longest walk.  Per-pixel results do not depend on the order.
+__device__ __forceinline__ uint32_t tile_pixel(uint32_t i, uint32_t w, uint32_t h) {
+    const uint32_t band = i / (8u * w);
+    const uint32_t y0 = 8u * band;
+    const uint32_t bh = h - y0 < 8u ? h - y0 : 8u;
+    const uint32_t j = i - y0 * w;       // index within the band of bh rows
+    const uint32_t ct = j / (8u * bh);   // tile column; tiles before it hold 8*bh pixels each
+    const uint32_t k = j - ct * 8u * bh;
+    const uint32_t tw = w - 8u * ct < 8u ? w - 8u * ct : 8u;
+    return (y0 + k / tw) * w + 8u * ct + k % tw;
+}
+
 __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
     uint32_t A = ctl->A;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
@@ -511,18 +529,20 @@ __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
         bool alive = false;
         uint32_t w = 0;
         if (i < q.npix) {
+            const uint32_t pix = tile_pixel(i, q.w, q.h);
             Ray R;
-            make_ray(q, vols[q.vol].n, i, R);
+            make_ray(q, vols[q.vol].n, pix, R);
             alive = R.entered != 0;
             w = alive ? ray_weight(R.te, R.tx) : 0u;
-            q.ray_state[i] = alive ? RAY_NOT_STARTED : RAY_DONE;
+            q.ray_state[pix] = alive ? RAY_NOT_STARTED : RAY_DONE;
+            q.act[1][i] = pix;
+            // the per-pixel clears cover every pixel once: by index
             q.image[i] = 0u;
             spr_hit h;
             h.t = __builtin_inf();
             h.block_id = NONE;
             h.cell = NONE;
             q.hits[i] = h;
-            q.act[1][i] = i;
             q.best[i] = ~0ull;       // per-pixel pass state: no hit, nothing deferred
             q.def_first[i] = NONE;
         }
@@ -791,11 +811,25 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
             }
             const uint32_t before = incl - found;
             const uint32_t total = (uint32_t)__shfl((int)incl, (int)(L - 1u), (int)L);
-            for (uint32_t k = 0; k < found; ++k)
-                if (before + k < nsr) {
-                    slots[before + k] = k < flushed ? sbuf[(size_t)k * SEG_BIG_LANES + bli] : s_slot[k - flushed][threadIdx.x];
-                    if (per_ray) pray[before + k] = i;
-                }
+            const uint32_t lim = before < nsr ? (found < nsr - before ? found : nsr - before) : 0u;
+            const uint32_t lim_col = lim < flushed ? lim : flushed;
+            // the column-buffer part 16 entries at a time, loads issued together
+            for (uint32_t k0 = 0; k0 < lim_col; k0 += 16) {
+                uint32_t v[16];
+#pragma unroll
+                for (uint32_t j = 0; j < 16; ++j)
+                    v[j] = k0 + j < lim_col ? sbuf[(size_t)(k0 + j) * SEG_BIG_LANES + bli] : 0u;
+#pragma unroll
+                for (uint32_t j = 0; j < 16; ++j)
+                    if (k0 + j < lim_col) {
+                        slots[before + k0 + j] = v[j];
+                        if (per_ray) pray[before + k0 + j] = i;
+                    }
+            }
+            for (uint32_t k = lim_col; k < lim; ++k) {
+                slots[before + k] = s_slot[k - flushed][threadIdx.x];
+                if (per_ray) pray[before + k] = i;
+            }
             if (seg == 0u) {
                 for (uint32_t k = total < nsr ? total : nsr; k < nsr; ++k) slots[k] = NONE;
                 if (total > 0 && T.pair_base[r] + rbase_i == 0) ctl->n_vis = 1u;

@@ -23,6 +23,7 @@ NONE = 0xFFFFFFFF
 DTYPE_F32, DTYPE_U8 = 0, 1
 CODEC_VERSION = 1
 NOALLOC_MAX_BLOCKS = 16384   # SPR_NOALLOC_MAX_BLOCKS
+MAX_EXTENT = 524288          # SPR_MAX_EXTENT: samples per volume axis, and bound on each eye coordinate
 SPEC_UNIFORM, SPEC_PER_RAY = 0, 1
 
 

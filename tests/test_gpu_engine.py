@@ -101,6 +101,34 @@ def test_short_stream_is_corrupt_and_bad_version_invalid():
     ctx.close()
 
 
+def test_extent_and_eye_limits_are_invalid():
+    """Volumes longer than MAX_EXTENT samples on an axis and eyes farther than
+    MAX_EXTENT on a coordinate are rejected (the traversal's block estimate is
+    exact within these limits); the limits themselves are accepted."""
+    from paper_2309_10212_amd import spr
+    ctx = spr.Context(device=0, cache_bytes=1 << 20)
+    s, dims = _tiny()
+    with pytest.raises(spr.SprError) as e:
+        ctx.load_volume(s, (spr.MAX_EXTENT + 1, 2, 2), 8)
+    assert e.value.status == -1
+    vol = ctx.load_volume(s, dims, 8)
+    c = dims[0] / 2.0
+    for eye, ok in [((spr.MAX_EXTENT + 1.0, c, c), False), ((c, c, -spr.MAX_EXTENT - 0.5), False),
+                    ((float(spr.MAX_EXTENT), c, c), True)]:
+        cam = volgen.Camera(eye=eye, center=(c, c, c), up=(0.0, 0.0, 1.0) if eye[2] == c else (0.0, 1.0, 0.0),
+                            vfov_deg=0.01)
+        if ok:
+            r = spr.Render(vol, cam, 0.5, 8, 8)
+            r.run()
+            r.free()
+        else:
+            with pytest.raises(spr.SprError) as e:
+                spr.Render(vol, cam, 0.5, 8, 8)
+            assert e.value.status == -1
+    vol.free()
+    ctx.close()
+
+
 @pytest.mark.parametrize("fail_after", [0, 1, 3, 6])
 def test_failing_allocator_gives_oom_and_leaks_nothing(fail_after):
     from paper_2309_10212_amd import spr

@@ -198,6 +198,26 @@ def test_sparse_volume_empty_space_jumps(ctx, cap):
     vol.free()
 
 
+def test_far_eye_at_the_extent_limit(ctx):
+    """Eyes at the coordinate limit: ray parameters near 10^6 samples, where the
+    traversal's fp32 block estimates carry their largest error."""
+    from paper_2309_10212_amd import spr
+    n = 64
+    s = volgen.encode(volgen.blobs(n, n, n, 5), 8)
+    dec = oracle.decode_volume(s, (n, n, n), 8)
+    vol = ctx.load_volume(s, (n, n, n), 8)
+    lim = float(spr.MAX_EXTENT)
+    for eye in [(lim, 0.61 * lim, -0.37 * lim), (-lim, -lim, lim)]:
+        cam = volgen.Camera(eye=eye, center=(31.3, 29.7, 33.1), up=(0.0, 0.0, 1.0), vfov_deg=0.006)
+        r = spr.Render(vol, cam, 0.5, 48, 40, spec_cap=8)
+        r.run()
+        ref = oracle.render(dec, cam, 0.5, 48, 40)
+        assert np.isfinite(ref["t"]).sum() > 100
+        _cmp_hits(r.hits(), r.image(), ref, f"far eye {eye}")
+        r.free()
+    vol.free()
+
+
 def test_ragged_volume_inside_camera_and_edges(ctx):
     from paper_2309_10212_amd import spr
     dims = (37, 29, 23)
