@@ -698,10 +698,15 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
             if (++steps > max_steps) { alive = false; guard_hit = true; break; }   // every step advances an index
             ++csteps;
             if (tcur >= t_hi && !fresh) { seg_done = true; break; }   // the rest is the next lane's
+            // The distance byte alone says whether the cell is empty (0 exactly for
+            // a cell with a candidate block): it is loaded first and tested first,
+            // so an empty cell's jump waits only for it.  The distances are 1 byte
+            // per coarse cell (2 MB at 2048x2048x1920, mostly L2 hits), the mask
+            // words 8 B (mostly misses).
             const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
-            const uint64_t cm = cmask[cid];
             const int cd = cdist[cid];
-            if (cm == 0) {
+            const uint64_t cm = cmask[cid];
+            if (cd != 0) {
                 bvalid = false;
                 fresh = false;   // the walk moves on to plane crossings
                 if (cd >= 2) {
