@@ -914,41 +914,24 @@ __global__ __launch_bounds__(256) void k_dedupe(PassCtl *ctl, Table T, const Vol
                 vol[k] = q.vol;
             }
         }
-        // Ranks.  Adjacent rays share blocks, so a wave's lanes often name
-        // the same block: the lanes of one block form a group, its first lane
-        // adds the group's size to the block's counter, and the members take
-        // consecutive ranks from the returned base.  One atomic per distinct
-        // block of the wave instead of one per pair; the ranks of a block are
-        // still exactly 0 .. count-1.
-        const uint32_t lane = lane_id();
+        // Ranks: one atomic per pair on its block's counter, the DD_ITEMS
+        // atomics of a thread issued together; the ranks of a block are
+        // exactly 0 .. count-1 in some order.
+        uint32_t rank[DD_ITEMS];
 #pragma unroll
         for (int k = 0; k < DD_ITEMS; ++k) {
-            const bool valid = b[k] != NONE;
-            if (valid) bi[k] = bidx(vol_state(vols[vol[k]]), b[k]);
-            const uint64_t key = ((uint64_t)vol[k] << 32) | b[k];
-            uint64_t todo = __ballot(valid);
-            uint32_t leader = 0, within = 0, gsize = 0;
-            while (todo != 0ull) {   // once per distinct block of the wave
-                const uint32_t l = (uint32_t)__builtin_ctzll(todo);
-                const uint64_t lk = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(key >> 32), (int)l) << 32) |
-                                    (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)key, (int)l);
-                const uint64_t m = __ballot(valid && key == lk);
-                if ((m >> lane) & 1ull) {
-                    leader = l;
-                    within = (uint32_t)__popcll(m & lanemask_lt());
-                }
-                if (lane == l) gsize = (uint32_t)__popcll(m);
-                todo &= ~m;
+            rank[k] = NONE;
+            if (b[k] != NONE) {
+                bi[k] = bidx(vol_state(vols[vol[k]]), b[k]);
+                rank[k] = __hip_atomic_fetch_add(as_global(vols[vol[k]].blk_cnt) + bi[k], 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
             }
-            uint32_t base = 0;
-            if (valid && lane == leader)
-                base = __hip_atomic_fetch_add(as_global(vols[vol[k]].blk_cnt) + bi[k], gsize, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-            base = (uint32_t)__shfl((int)base, (int)leader);
-            if (!valid) continue;
-            const uint32_t rank = base + within;
-            W.pair_rank[x0 + (uint32_t)k * 256u + threadIdx.x] = rank;
-            if (rank == 0) {
+        }
+#pragma unroll
+        for (int k = 0; k < DD_ITEMS; ++k) {
+            if (b[k] == NONE) continue;
+            W.pair_rank[x0 + (uint32_t)k * 256u + threadIdx.x] = rank[k];
+            if (rank[k] == 0) {
                 if (b[k] == b0 && vol[k] == vol0) {
                     W.vis_list[0] = ((uint64_t)vol0 << 32) | b0;
                     vols[vol0].vis_idx[bi[k]] = 0u;
@@ -1698,16 +1681,6 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
         s_wsum[r] = 0;
     }
     __syncthreads();
-    // the survivors' weights, per request (thread-strided over the waves)
-    if (nw > 0) {
-        uint32_t r = find_req(T.act_base, nreq, (t < nw ? t : 0u) << 6);
-        for (uint32_t w = t; w < nw; w += PE_THREADS) {
-            const uint32_t ww = T.wave_w[w];
-            if (!ww) continue;
-            while (r + 1 < nreq && T.act_base[r + 1] <= (w << 6)) ++r;
-            atomicAdd(&s_wsum[r], (unsigned long long)ww);
-        }
-    }
     const uint32_t per = (nw + PE_THREADS - 1) / PE_THREADS;
     const uint32_t w0 = t * per < nw ? t * per : nw;
     const uint32_t w1 = w0 + per < nw ? w0 + per : nw;
@@ -1724,6 +1697,7 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
         uint32_t next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
         uint32_t rbase = T.act_base[r], rna = T.reqs[r].st->n_act_prev;
         uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+        unsigned long long accw = 0ull;   // the survivors' weights (per-ray counts)
         // survivors of wave w: the initial pass records them; a pass records
         // its terminations, and the wave's active rays are the request's
         // n_act_prev rays from its 64-aligned start
@@ -1733,13 +1707,15 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
             const uint32_t act = lo >= rna ? 0u : (rna - lo < 64u ? rna - lo : 64u);
             return act - v.w;
         };
-        auto add = [&](uint32_t w, const uint4 v) -> uint32_t {
+        auto add = [&](uint32_t w, const uint4 v, uint32_t ww) -> uint32_t {
             while (w >= next) {   // crossing into the next request's waves
                 if (acc.x) atomicAdd(&s_req[0][r], acc.x);
                 if (acc.y) atomicAdd(&s_req[1][r], acc.y);
                 if (acc.z) atomicAdd(&s_req[2][r], acc.z);
                 if (acc.w) atomicAdd(&s_req[3][r], acc.w);
+                if (accw) atomicAdd(&s_wsum[r], accw);
                 acc = make_uint4(0u, 0u, 0u, 0u);
+                accw = 0ull;
                 ++r;
                 next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
                 rbase = T.act_base[r];
@@ -1747,6 +1723,7 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
             }
             const uint32_t sv = survivors(w, v);
             acc.x += sv; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+            accw += ww;
             run += sv;
             return sv;
         };
@@ -1754,20 +1731,24 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
 #pragma unroll
             for (uint32_t h = 0; h < PE_REG; h += PE_HALF) {
                 uint4 rv[PE_HALF];
+                uint32_t wv[PE_HALF];
 #pragma unroll
-                for (uint32_t k = 0; k < PE_HALF; ++k)
+                for (uint32_t k = 0; k < PE_HALF; ++k) {
                     rv[k] = (w0 + h + k < w1) ? T.wave_rec[w0 + h + k] : make_uint4(0u, 0u, 0u, 0u);
+                    wv[k] = (w0 + h + k < w1) ? T.wave_w[w0 + h + k] : 0u;
+                }
 #pragma unroll
                 for (uint32_t k = 0; k < PE_HALF; ++k)
-                    surv[h + k] = (w0 + h + k < w1) ? add(w0 + h + k, rv[k]) : 0u;
+                    surv[h + k] = (w0 + h + k < w1) ? add(w0 + h + k, rv[k], wv[k]) : 0u;
             }
         } else {
-            for (uint32_t w = w0; w < w1; ++w) (void)add(w, T.wave_rec[w]);
+            for (uint32_t w = w0; w < w1; ++w) (void)add(w, T.wave_rec[w], T.wave_w[w]);
         }
         if (acc.x) atomicAdd(&s_req[0][r], acc.x);
         if (acc.y) atomicAdd(&s_req[1][r], acc.y);
         if (acc.z) atomicAdd(&s_req[2][r], acc.z);
         if (acc.w) atomicAdd(&s_req[3][r], acc.w);
+        if (accw) atomicAdd(&s_wsum[r], accw);
     }
     // workgroup exclusive scan of the run totals
     const uint32_t l = lane_id(), wv = t >> 6;
