@@ -77,7 +77,7 @@ def kernel_bytes(name, c, rate):
         "k_init_rays": 40 * NP,                    # ray state, image, hit record, active entry, pass state
         # active entry + state in; candidate count, slot base and count out; slots written; per coarse cell
         # visited its isovalue-mask word and empty-space distance
-        "k_traverse": 20 * A + 4 * S + 9 * c.get("coarse_steps", 0),
+        "k_traverse": 20 * A + 4 * S + c.get("coarse_steps", 0) + 8 * c.get("coarse_masks", 0),
         "k_dedupe": 4 * S + 12 * P + 12 * V,
         "k_mark": 52 * V + 12 * K + 8 * M,      # + the 8 neighbour stamps each visible block tests
         "k_assign_scatter": 32 * M + 4 * S + 28 * Ps,

@@ -142,8 +142,10 @@ typedef struct {
     uint64_t walk_guard;      /* ray walks (traversal or block raytrace) ended by a step guard instead of
                                  by leaving the domain, the block, or finding their blocks; every step
                                  advances a cell index, so this is 0 unless the walk logic is broken */
-    uint64_t coarse_steps;    /* coarse cells the traversal visited (Sec. 3.3): one macrocell word (the
-                                 isovalue mask and the empty-space distance) read per visit */
+    uint64_t coarse_steps;    /* coarse cells the traversal visited (Sec. 3.3): the empty-space distance
+                                 byte read per visit */
+    uint64_t coarse_masks;    /* of those, the cells with a candidate block, whose isovalue mask word
+                                 is read too */
 } spr_counters;
 
 /* Per-render summary. */

@@ -606,6 +606,7 @@ spr_status spr_ctx_counters(spr_ctx *c, spr_counters *o) {
     o->max_active_blocks = p.acc_max_active;
     o->walk_guard = p.acc_guard;
     o->coarse_steps = p.acc_csteps;
+    o->coarse_masks = p.acc_cmasks;
     return SPR_OK;
 }
 

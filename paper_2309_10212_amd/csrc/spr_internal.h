@@ -196,12 +196,13 @@ struct PassCtl {
     uint32_t A_trav;            // traversal lane space of this pass (64-padded per request)
     uint32_t guard;             // walks ended by a step guard (never by construction: every
                                 // step advances a cell index within the domain)
-    uint32_t csteps;            // coarse cells the traversal visited (one mask word and distance read each)
-    uint32_t pad[5];
+    uint32_t csteps;            // coarse cells the traversal visited (one distance byte read each)
+    uint32_t cmasks;            // of those, the nonempty ones (their mask word read too)
+    uint32_t pad[4];
     uint32_t hist[64];
     // cumulative counters since context creation
     unsigned long long acc_passes, acc_decoded, acc_visible, acc_active, acc_pairs, acc_evicted, acc_overflow,
-        acc_rays, acc_slots, acc_served, acc_max_active, acc_guard, acc_csteps;
+        acc_rays, acc_slots, acc_served, acc_max_active, acc_guard, acc_csteps, acc_cmasks;
 };
 
 // Launch table of a pass: the requests advanced together.

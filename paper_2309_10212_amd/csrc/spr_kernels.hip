@@ -332,6 +332,7 @@ __global__ __launch_bounds__(64) void k_pass_begin(PassCtl *ctl, Table T, int is
     ctl->evict_done_blocks = 0; ctl->evicted = 0; ctl->terminated = 0; ctl->pairs = 0; ctl->overflow = 0;
     ctl->guard = 0;
     ctl->csteps = 0;
+    ctl->cmasks = 0;
     ctl->rays = rays;
     T.act_base[nreq] = A;
     T.pair_base[nreq] = P;
@@ -693,7 +694,8 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         // jump or a coarse step.  Inner loop: the blocks of a nonempty coarse
         // cell, no memory access but the LDS staging.
         bool guard_hit = false;
-        uint32_t csteps = 0;   // coarse cells visited (mask word and distance loaded)
+        uint32_t csteps = 0;   // coarse cells visited (distance loaded)
+        uint32_t cmasks = 0;   // nonempty coarse cells visited (mask word loaded too)
         while (alive && found < nsr) {
             if (++steps > max_steps) { alive = false; guard_hit = true; break; }   // every step advances an index
             ++csteps;
@@ -746,6 +748,7 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                 }
                 continue;
             }
+            ++cmasks;
             if (!bvalid) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -862,16 +865,19 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         for (int bit = 0; bit < 13; ++bit)   // found <= ns <= 4096: a sum of bit planes over the lanes
             wpairs += (uint32_t)__popcll(__ballot(lead && ((found >> bit) & 1u))) << bit;
         const uint32_t wterm = (uint32_t)__popcll(__ballot(term));
-        uint32_t wsteps = 0;
+        uint32_t wsteps = 0, wmasks = 0;
 #pragma unroll
-        for (int bit = 0; bit < 16; ++bit)   // csteps <= max_steps < 2^16
+        for (int bit = 0; bit < 16; ++bit) {   // csteps, cmasks <= max_steps < 2^16
             wsteps += (uint32_t)__popcll(__ballot((csteps >> bit) & 1u)) << bit;
+            wmasks += (uint32_t)__popcll(__ballot((cmasks >> bit) & 1u)) << bit;
+        }
         const uint64_t act = __ballot(1);
         if ((int)lane_id() == __ffsll((unsigned long long)act) - 1) {
             uint4 *rec = T.wave_rec + ((uni(T.act_base[r]) + i) >> 6);
             if (wpairs) atomicAdd(&rec->y, wpairs);
             if (wterm) atomicAdd(&rec->w, wterm);
             if (wsteps) atomicAdd(&ctl->csteps, wsteps);
+            if (wmasks) atomicAdd(&ctl->cmasks, wmasks);
         }
     }
 }
@@ -1813,6 +1819,7 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
             if (ctl->n_actblk > ctl->acc_max_active) ctl->acc_max_active = ctl->n_actblk;
             ctl->acc_guard += ctl->guard;
             ctl->acc_csteps += ctl->csteps;
+            ctl->acc_cmasks += ctl->cmasks;
         }
     }
     for (uint32_t r = t; r < nreq; r += PE_THREADS) {

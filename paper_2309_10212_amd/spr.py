@@ -73,7 +73,7 @@ class PassStats(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("passes", "blocks_decoded", "visible_blocks", "active_blocks",
                                                "pairs", "evicted", "overflow", "rays", "pair_slots",
-                                               "served_pairs", "max_active_blocks", "walk_guard", "coarse_steps")]
+                                               "served_pairs", "max_active_blocks", "walk_guard", "coarse_steps", "coarse_masks")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

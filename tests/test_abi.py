@@ -63,3 +63,31 @@ def test_struct_layouts_match_header():
     assert spr.HIT_DTYPE.itemsize == 16
     assert ctypes.sizeof(spr._Camera) == 80
     assert ctypes.sizeof(spr._VolumeDesc) == 24
+
+
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """Every ctypes mirror has the size and field offsets gcc gives the
+    header's struct (a C program built from include/spr.h prints them)."""
+    import subprocess
+    from paper_2309_10212_amd import spr
+    pairs = [("spr_allocator", spr._Allocator), ("spr_config", spr._Config), ("spr_volume_desc", spr._VolumeDesc),
+             ("spr_camera", spr._Camera), ("spr_pass_stats", spr.PassStats), ("spr_counters", spr.Counters),
+             ("spr_render_info", spr.RenderInfo), ("spr_mem_split", spr.MemSplit), ("spr_tuning", spr.Tuning),
+             ("spr_member_state", spr.MemberState), ("spr_kernel_time", spr.KernelTime)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "spr.h"', 'int main(void) {']
+    for cname, cls in pairs:
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            cf = {"pass_": "pass"}.get(fname, fname)
+            lines.append(f'  printf("{cname}.{fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    for cname, cls in pairs:
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
