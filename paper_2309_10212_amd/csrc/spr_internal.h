@@ -349,6 +349,39 @@ __device__ __forceinline__ uint32_t block_bump(uint32_t *counter, uint32_t cnt, 
     return r;
 }
 
+// block_bump for two counters at once (one scan, both atomics issued by one
+// lane back to back): returns the starts of the thread's runs of na entries
+// on *ca and nb entries on *cb.  s_tmp: BS/64 + 1 entries.
+template <int BS>
+__device__ __forceinline__ uint2 block_bump2(uint32_t *ca, uint32_t na, uint32_t *cb, uint32_t nb, uint2 *s_tmp) {
+    static_assert(BS % 64 == 0 && BS <= 4096, "block_bump2: workgroup of whole waves, at most 64 of them");
+    constexpr uint32_t NW = BS / 64;
+    const uint32_t l = lane_id(), w = threadIdx.x >> 6;
+    uint32_t ia = na, ib = nb;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t oa = __shfl_up(ia, off), ob = __shfl_up(ib, off);
+        if ((int)l >= off) { ia += oa; ib += ob; }
+    }
+    if (l == 63) s_tmp[w] = make_uint2(ia, ib);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint2 v = l < NW ? s_tmp[l] : make_uint2(0u, 0u);
+        uint32_t xa = v.x, xb = v.y;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t oa = __shfl_up(xa, off), ob = __shfl_up(xb, off);
+            if ((int)l >= off) { xa += oa; xb += ob; }
+        }
+        if (l < NW) s_tmp[l] = make_uint2(xa - v.x, xb - v.y);
+        if (l == 63) s_tmp[NW] = make_uint2(xa ? atomicAdd(ca, xa) : 0u, xb ? atomicAdd(cb, xb) : 0u);
+    }
+    __syncthreads();
+    const uint2 r = make_uint2(s_tmp[NW].x + s_tmp[w].x + ia - na, s_tmp[NW].y + s_tmp[w].y + ib - nb);
+    __syncthreads();   // s_tmp may be reused right away
+    return r;
+}
+
 // Wave-aggregated append: every active lane calls it; lanes with want get
 // consecutive indices from one atomic on *counter.
 __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool want) {
@@ -577,8 +610,10 @@ __device__ inline bool advance(const Ray &R, const Level &lv, int c[3], double t
 
 struct CellHit {
     int hit;
+    int refine;          // the root lies inside the bracket below: refine_hit finds it
     double s;
     double loc[3];
+    double A, B, C, D, sa, sb, ga;
 };
 
 __device__ __forceinline__ double horner3(double A, double B, double C, double D, double s) {
@@ -686,6 +721,7 @@ __device__ inline void test_cell(const Ray &R, const int c[3], double t0, double
     // strict sign change wins
     double sp = 0.0;
     double gp = horner3(A, B, C, D, 0.0);
+    res.refine = 0;
     if (gp == 0.0) { res.hit = 1; res.s = 0.0; return; }
 #pragma unroll
     for (int k = 1; k <= 3; ++k) {
@@ -693,14 +729,24 @@ __device__ inline void test_cell(const Ray &R, const int c[3], double t0, double
         const double sk = k == ne + 1 ? S : (k == 1 ? e0 : e1);
         const double gk = horner3(A, B, C, D, sk);
         if ((gp < 0.0 && gk > 0.0) || (gp > 0.0 && gk < 0.0)) {
+            // the root is left to refine_hit, which the raytrace calls after its
+            // cell loop: the lanes of a wave that hit then refine together
             res.hit = 1;
-            res.s = refine_root(A, B, C, D, sp, sk, gp);
+            res.refine = 1;
+            res.A = A; res.B = B; res.C = C; res.D = D;
+            res.sa = sp; res.sb = sk; res.ga = gp;
+            res.s = sp;
             return;
         }
         if (gk == 0.0) { res.hit = 1; res.s = sk; return; }
         sp = sk;
         gp = gk;
     }
+}
+
+// The hit's position in its cell when test_cell left it to a bracket.
+__device__ __forceinline__ void refine_hit(CellHit &h) {
+    if (h.refine) h.s = refine_root(h.A, h.B, h.C, h.D, h.sa, h.sb, h.ga);
 }
 
 // Headlight Lambertian shading of the hit: base colour (0.90, 0.75, 0.40) x

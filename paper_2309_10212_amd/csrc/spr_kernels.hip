@@ -976,7 +976,7 @@ __device__ __forceinline__ uint32_t admitted_blocks(const PassCtl *ctl) {
 }
 
 __global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, Work W, Cache C) {
-    __shared__ uint32_t s_tmp[256 / 64 + 1];
+    __shared__ uint2 s_tmp2[256 / 64 + 1];
     __shared__ uint32_t s_def, s_act;
     const uint32_t nv = ctl->n_vis;
     const uint32_t vadm = admitted_blocks(ctl);
@@ -1064,9 +1064,9 @@ __global__ __launch_bounds__(256) void k_mark(PassCtl *ctl, const VolDev *vols, 
                 my_def += cnt;
             }
         }
-        const uint32_t off = block_bump<256>(&ctl->cursor, j < vadm ? cnt : 0u, s_tmp);
-        if (j < vadm) W.vis_off[j] = off;
-        uint32_t mi = block_bump<256>(&ctl->n_miss, nmiss, s_tmp);
+        const uint2 om = block_bump2<256>(&ctl->cursor, j < vadm ? cnt : 0u, &ctl->n_miss, nmiss, s_tmp2);
+        if (j < vadm) W.vis_off[j] = om.x;
+        uint32_t mi = om.y;
         if (missmask) {
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
@@ -1538,10 +1538,11 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
             double t0 = cell_entry(R, L1, c);
             struct { double t; uint32_t cell, rgba; } out = {__builtin_inf(), NONE, 0u};
             int guard = 0;
+            float fc[8];
+            CellHit h;
             for (; guard < 16; ++guard) {   // at most 10 cells of a 4^3 block lie on a ray
                 const double tx = cell_exit(R, L1, c);
                 const double t1 = tx < R.tx ? tx : R.tx;
-                float fc[8];
                 int lx = c[0] - lo[0], ly = c[1] - lo[1], lz = c[2] - lo[2];
                 if (staged) {
                     const float *g = s_grid[lb];
@@ -1553,18 +1554,22 @@ __global__ __launch_bounds__(RT_TILE, 3) void k_raytrace(PassCtl *ctl, Table T, 
                     for (int k = 0; k < 8; ++k)
                         fc[k] = slot_value(C.slots, nsl, lx + (k & 1), ly + ((k >> 1) & 1), lz + (k >> 2));
                 }
-                CellHit h;
                 test_cell(R, c, t0, t1, fc, q.iso, h);
                 if (h.hit) {
-                    out.t = t0 + h.s;
                     out.cell = (uint32_t)(lx + 4 * ly + 16 * lz);
-                    out.rgba = shade_hit(R, h, fc);
                     break;
                 }
                 if (tx > R.tx || !advance(R, L1, c, tx, lo, hi)) break;
                 t0 = tx;
             }
             if (guard == 16) atomicAdd(&ctl->guard, 1u);
+            // root and colour of the hit after the loop, where the wave's hit
+            // lanes run them together (t0 and fc are still the hit cell's)
+            if (out.cell != NONE) {
+                refine_hit(h);
+                out.t = t0 + h.s;
+                out.rgba = shade_hit(R, h, fc);
+            }
             pair_done(q, pix, qq, out.cell, out.rgba, out.t);
         }
         __syncthreads();   // the next tile reuses the LDS
@@ -1642,15 +1647,13 @@ __global__ __launch_bounds__(256, 3) void k_raytrace_direct(PassCtl *ctl, Table 
         double out_t = __builtin_inf();
         uint32_t out_cell = NONE, out_rgba = 0u;
         int guard = 0;
+        CellHit h;
         for (; guard < 16; ++guard) {   // at most 10 cells of a 4^3 block lie on a ray
             const double tx = cell_exit(R, L1, c);
             const double t1 = tx < R.tx ? tx : R.tx;
-            CellHit h;
             test_cell(R, c, t0, t1, fc, iso, h);
             if (h.hit) {
-                out_t = t0 + h.s;
                 out_cell = (uint32_t)((c[0] - lo[0]) + 4 * (c[1] - lo[1]) + 16 * (c[2] - lo[2]));
-                out_rgba = shade_hit(R, h, fc);
                 break;
             }
             if (tx > R.tx || !advance(R, L1, c, tx, lo, hi)) break;
@@ -1658,6 +1661,13 @@ __global__ __launch_bounds__(256, 3) void k_raytrace_direct(PassCtl *ctl, Table 
             t0 = tx;
         }
         if (guard == 16) atomicAdd(&ctl->guard, 1u);
+        // root and colour of the hit after the loop, where the wave's hit lanes
+        // run them together (t0 and fc are still the hit cell's)
+        if (out_cell != NONE) {
+            refine_hit(h);
+            out_t = t0 + h.s;
+            out_rgba = shade_hit(R, h, fc);
+        }
         pair_done(q, pix, qq, out_cell, out_rgba, out_t);
     }
 }
