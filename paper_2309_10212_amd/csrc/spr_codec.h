@@ -187,11 +187,18 @@ template <int RWMAX>
 __device__ __forceinline__ bool thread_decode(const uint32_t *__restrict__ rec, int rate, DecodeLds<RWMAX> &L,
                                               uint32_t lane, int32_t (&q)[64], int &e_out) {
     const uint32_t rw = 2u * (uint32_t)rate;
-    const uint32_t w0 = rec[0];
+    // the record lives in global memory: global (not flat) loads, all issued
+    // before the LDS stores, so the words arrive in one round trip
+    typedef const __attribute__((address_space(1))) uint32_t *grec_t;
+    const grec_t g = (grec_t)rec;
+    const uint32_t w0 = g[0];
     if (!(w0 & 1u)) return false;
+    uint32_t words[RWMAX + 1];
+#pragma unroll
+    for (int j = 1; j < RWMAX + 2; ++j) words[j - 1] = (uint32_t)j < rw ? g[j] : 0u;
     L.rec[lane] = w0;
 #pragma unroll
-    for (int j = 1; j < RWMAX + 2; ++j) L.rec[j * 64 + lane] = (uint32_t)j < rw ? rec[j] : 0u;
+    for (int j = 1; j < RWMAX + 2; ++j) L.rec[j * 64 + lane] = words[j - 1];
     e_out = (int)((w0 >> 1) & 0xFFu) - 127;
     const uint32_t B = 64u * (uint32_t)rate;
 

@@ -12,13 +12,16 @@
 
 namespace spr {
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 // Decode one block to 64 floats, stored with 16-byte stores to dst (raster order).
 template <int RWMAX>
 __device__ __forceinline__ void decode_to(const uint32_t *__restrict__ rec, int rate, DecodeLds<RWMAX> &L, uint32_t lane,
                                           float *__restrict__ dst) {
-    float4 *d4 = reinterpret_cast<float4 *>(dst);
+    // global-address 16-byte stores (a flat store would also wait on the LDS counter)
+    const gptr<f4v> d4 = as_global(reinterpret_cast<f4v *>(dst));
     if (rate == 32) {
-        const float4 *s4 = reinterpret_cast<const float4 *>(rec);
+        const gptr<const f4v> s4 = as_global(reinterpret_cast<const f4v *>(rec));
 #pragma unroll
         for (int i = 0; i < 16; ++i) d4[i] = s4[i];
         return;
@@ -27,7 +30,7 @@ __device__ __forceinline__ void decode_to(const uint32_t *__restrict__ rec, int 
     int e = 0;
     if (!thread_decode<RWMAX>(rec, rate, L, lane, q, e)) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) d4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int i = 0; i < 16; ++i) d4[i] = f4v{0.f, 0.f, 0.f, 0.f};
         return;
     }
     if (e >= -99) {
@@ -35,13 +38,13 @@ __device__ __forceinline__ void decode_to(const uint32_t *__restrict__ rec, int 
         // power-of-two scale equals the single rounding of q * 2^(e-27)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
-            d4[i] = make_float4(ldexpf((float)q[4 * i], e - 27), ldexpf((float)q[4 * i + 1], e - 27),
-                                ldexpf((float)q[4 * i + 2], e - 27), ldexpf((float)q[4 * i + 3], e - 27));
+            d4[i] = f4v{ldexpf((float)q[4 * i], e - 27), ldexpf((float)q[4 * i + 1], e - 27),
+                        ldexpf((float)q[4 * i + 2], e - 27), ldexpf((float)q[4 * i + 3], e - 27)};
     } else {
 #pragma unroll
         for (int i = 0; i < 16; ++i)
-            d4[i] = make_float4((float)ldexp((double)q[4 * i], e - 27), (float)ldexp((double)q[4 * i + 1], e - 27),
-                                (float)ldexp((double)q[4 * i + 2], e - 27), (float)ldexp((double)q[4 * i + 3], e - 27));
+            d4[i] = f4v{(float)ldexp((double)q[4 * i], e - 27), (float)ldexp((double)q[4 * i + 1], e - 27),
+                        (float)ldexp((double)q[4 * i + 2], e - 27), (float)ldexp((double)q[4 * i + 3], e - 27)};
     }
 }
 
@@ -1711,7 +1714,7 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
     if (w0 < w1) {
         uint32_t r = find_req(T.act_base, nreq, w0 << 6);
         uint32_t next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
-        uint32_t rbase = T.act_base[r], rna = T.reqs[r].st->n_act_prev;
+        uint32_t rbase = T.act_base[r], rna = as_global(T.reqs[r].st)->n_act_prev;
         uint4 acc = make_uint4(0u, 0u, 0u, 0u);
         unsigned long long accw = 0ull;   // the survivors' weights (per-ray counts)
         // survivors of wave w: the initial pass records them; a pass records
@@ -1735,7 +1738,7 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
                 ++r;
                 next = (r + 1 < nreq) ? (T.act_base[r + 1] >> 6) : 0xFFFFFFFFu;
                 rbase = T.act_base[r];
-                rna = T.reqs[r].st->n_act_prev;
+                rna = as_global(T.reqs[r].st)->n_act_prev;
             }
             const uint32_t sv = survivors(w, v);
             acc.x += sv; acc.y += v.y; acc.z += v.z; acc.w += v.w;
@@ -1798,7 +1801,7 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
             const uint4 v = T.wave_rec[w];
             uint32_t sv = v.x;
             if (!is_init) {
-                const uint32_t lo = (w << 6) - T.act_base[r], rna = T.reqs[r].st->n_act_prev;
+                const uint32_t lo = (w << 6) - T.act_base[r], rna = as_global(T.reqs[r].st)->n_act_prev;
                 sv = (lo >= rna ? 0u : (rna - lo < 64u ? rna - lo : 64u)) - v.w;
             }
             T.wave_off[w] = off;
@@ -1833,23 +1836,28 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
         }
     }
     for (uint32_t r = t; r < nreq; r += PE_THREADS) {
-        ReqDev &q = T.reqs[r];
-        ReqState *st = q.st;
+        // every field read first, through a global-address pointer, then every
+        // store: no wait between the stores and the loads after them
+        const ReqDev &q = T.reqs[r];
+        const gptr<ReqState> st = as_global(q.st);
+        const uint32_t npix = q.npix, cap = q.spec_cap;
+        const uint32_t prev = st->n_act_prev, cur = st->cur, cursor = st->slot_cursor;
+        const unsigned long long tot = st->tot_pairs;
         const uint32_t na = s_req[0][r];
-        if (st->n_act_prev > 0) st->cur ^= 1u;
+        uint32_t ns = 0;
+        if (na > 0) {
+            ns = npix / na;
+            if (ns < 1) ns = 1;
+            if (ns > cap) ns = cap;
+        }
+        st->cur = prev > 0 ? cur ^ 1u : cur;
         st->n_act = na;
         st->wsum = s_wsum[r];
-        st->last_slots = is_init ? 0u : st->slot_cursor;
+        st->last_slots = is_init ? 0u : cursor;
         st->last_pairs = s_req[1][r];
         st->last_deferred = s_req[2][r];
         st->last_terminated = s_req[3][r];
-        st->tot_pairs += s_req[1][r];
-        uint32_t ns = 0;
-        if (na > 0) {
-            ns = q.npix / na;
-            if (ns < 1) ns = 1;
-            if (ns > q.spec_cap) ns = q.spec_cap;
-        }
+        st->tot_pairs = tot + s_req[1][r];
         st->n_spec = ns;
     }
 }
