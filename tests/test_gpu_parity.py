@@ -218,6 +218,40 @@ def test_far_eye_at_the_extent_limit(ctx):
     vol.free()
 
 
+@pytest.mark.parametrize("cap", [1, 64])
+def test_exact_block_level_ties(ctx, cap):
+    """Rays through block corners and along block edges and faces: the centre
+    pixel of an odd image looks exactly along the view direction, here
+    (1,1,1)/sqrt3 from an integer eye (three planes crossed at one parameter at
+    every block corner), (1,0,0) on the planes y = 8, z = 12 (two parallel axes
+    on block planes) and (1,1,0)/sqrt2 (x and y planes crossed together).  The
+    image and every pass counter equal the oracle's."""
+    from paper_2309_10212_amd import spr
+    n = 48
+    s = volgen.encode(volgen.blobs(n, n, n, 4), 8)
+    dec = oracle.decode_volume(s, (n, n, n), 8)
+    vol = ctx.load_volume(s, (n, n, n), 8)
+    cams = [volgen.Camera(eye=(-8.0, -8.0, -8.0), center=(40.0, 40.0, 40.0), up=(0.0, 0.0, 1.0), vfov_deg=40.0),
+            volgen.Camera(eye=(-5.0, 8.0, 12.0), center=(30.0, 8.0, 12.0), up=(0.0, 1.0, 0.0), vfov_deg=40.0),
+            volgen.Camera(eye=(-8.0, -8.0, 20.0), center=(40.0, 40.0, 20.0), up=(0.0, 0.0, 1.0), vfov_deg=40.0)]
+    for ci, cam in enumerate(cams):
+        d, _, _, _ = oracle.ray((n, n, n), cam, 33, 33, 16, 16)
+        assert (d[0] == d[1] == d[2]) if ci == 0 else (d[1] == d[2] == 0.0 if ci == 1 else (d[0] == d[1] and d[2] == 0.0))
+        r = spr.Render(vol, cam, 0.5, 33, 33, spec_cap=cap)
+        sched = oracle.schedule(dec, cam, 0.5, 33, 33, cap)
+        got = []
+        while not r.done():
+            got.append(r.pass_(stats=True))
+            assert len(got) <= len(sched) + 2
+        _cmp_hits(r.hits(), r.image(), oracle.render(dec, cam, 0.5, 33, 33), f"tie camera {ci} cap {cap}")
+        assert len(got) == len(sched)
+        for p, (g, o) in enumerate(zip(got, sched)):
+            for k in ("n_active", "n_spec", "pairs", "visible", "active_blocks", "terminated"):
+                assert g[k] == o[k], (ci, p, k, g, o)
+        r.free()
+    vol.free()
+
+
 def test_ragged_volume_inside_camera_and_edges(ctx):
     from paper_2309_10212_amd import spr
     dims = (37, 29, 23)
