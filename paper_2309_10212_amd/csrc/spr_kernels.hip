@@ -765,41 +765,58 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
                 fresh = false;
             }
             cvalid = false;
-            while (true) {
-                if (tau >= t_hi) { seg_done = true; break; }
-                const bool emit = tau >= t_lo && ((cm >> local_bit(cb)) & 1ull);
-                if (emit) {
-                    const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * u.nb[1] + cb[1]) * u.nb[0] + cb[0]);
-                    s_slot[nbuf][threadIdx.x] = bid;
-                    found++;
-                    if (++nbuf == TR_BUF && (L == 1u || big)) {
-                        if (L == 1u) {
-                            for (uint32_t k = 0; k < TR_BUF; ++k) {
-                                slots[flushed + k] = s_slot[k][threadIdx.x];
-                                if (per_ray) pray[flushed + k] = i;
-                            }
-                        } else {
-                            gptr<uint32_t> d = sbuf + ((size_t)flushed * SEG_BIG_LANES + bli);
+            // One exit from the block loop, with its reason: a single exit mask
+            // for the compiler to keep instead of one per break.
+            //   1 the rest is the next lane's, 2 all slots filled, 3 step guard,
+            //   4 the ray left the volume, 5 the walk entered another coarse cell
+            int why = 0;
+            do {
+                if (tau >= t_hi) {
+                    why = 1;
+                } else {
+                    const bool emit = tau >= t_lo && ((cm >> local_bit(cb)) & 1ull);
+                    if (emit) {
+                        const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * u.nb[1] + cb[1]) * u.nb[0] + cb[0]);
+                        s_slot[nbuf][threadIdx.x] = bid;
+                        found++;
+                        if (++nbuf == TR_BUF && (L == 1u || big)) {
+                            if (L == 1u) {
+                                for (uint32_t k = 0; k < TR_BUF; ++k) {
+                                    slots[flushed + k] = s_slot[k][threadIdx.x];
+                                    if (per_ray) pray[flushed + k] = i;
+                                }
+                            } else {
+                                gptr<uint32_t> d = sbuf + ((size_t)flushed * SEG_BIG_LANES + bli);
 #pragma unroll 1
-                            for (uint32_t k = 0; k < TR_BUF; ++k, d += SEG_BIG_LANES) *d = s_slot[k][threadIdx.x];
+                                for (uint32_t k = 0; k < TR_BUF; ++k, d += SEG_BIG_LANES) *d = s_slot[k][threadIdx.x];
+                            }
+                            flushed += TR_BUF;
+                            nbuf = 0;
                         }
-                        flushed += TR_BUF;
-                        nbuf = 0;
                     }
-                    if (found == nsr) break;
+                    if (found == nsr) {
+                        why = 2;
+                    } else if (++steps > max_steps) {
+                        why = 3;
+                    } else {
+                        const double tn = walk_exit(wb);
+                        if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) {
+                            why = 4;
+                        } else {
+                            tcur = tn;
+                            tau = tn;
+                            if ((cb[0] >> 2) != cc[0] || (cb[1] >> 2) != cc[1] || (cb[2] >> 2) != cc[2]) why = 5;
+                        }
+                    }
                 }
-                if (++steps > max_steps) { alive = false; guard_hit = true; break; }
-                double tn = walk_exit(wb);
-                if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) { alive = false; break; }
-                tcur = tn;
-                tau = tn;
-                if ((cb[0] >> 2) != cc[0] || (cb[1] >> 2) != cc[1] || (cb[2] >> 2) != cc[2]) {
+            } while (why == 0);
+            if (why == 1) break;
+            if (why == 3) { alive = false; guard_hit = true; break; }
+            if (why == 4) { alive = false; break; }
+            if (why == 5) {
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
-                    break;
-                }
+                for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
             }
-            if (seg_done) break;
         }
         if (guard_hit) atomicAdd(&ctl->guard, 1u);   // counted, so that tests can assert it never happens
         // The block of pair 0 (the first active ray's first candidate) takes
