@@ -688,7 +688,6 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
             }
         }
         double tau = tcur;    // entry parameter of the current block
-        bool seg_done = false;
         uint32_t nbuf = 0, flushed = 0;   // candidates staged in LDS / already written
         const int max_steps = u.tb[0] + u.tb[1] + u.tb[2] + u.tc[0] + u.tc[1] + u.tc[2] + 16;
         int steps = 0;
@@ -699,125 +698,136 @@ __global__ __launch_bounds__(256) void k_traverse(PassCtl *ctl, Table T, const V
         bool guard_hit = false;
         uint32_t csteps = 0;   // coarse cells visited (distance loaded)
         uint32_t cmasks = 0;   // nonempty coarse cells visited (mask word loaded too)
-        while (alive && found < nsr) {
-            if (++steps > max_steps) { alive = false; guard_hit = true; break; }   // every step advances an index
-            ++csteps;
-            if (tcur >= t_hi && !fresh) { seg_done = true; break; }   // the rest is the next lane's
-            // The distance byte alone says whether the cell is empty (0 exactly for
-            // a cell with a candidate block): it is loaded first and tested first,
-            // so an empty cell's jump waits only for it.  The distances are 1 byte
-            // per coarse cell (2 MB at 2048x2048x1920, mostly L2 hits), the mask
-            // words 8 B (mostly misses).
-            const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
-            const int cd = cdist[cid];
-            const uint64_t cm = cmask[cid];
-            if (cd != 0) {
-                bvalid = false;
-                fresh = false;   // the walk moves on to plane crossings
-                if (cd >= 2) {
-                    // every coarse cell within cd-1 (chessboard) is empty: leave that box
-                    // in one jump.  t* = the first crossing of one of its faces (or of
-                    // the domain) - the parameter at which a cell-by-cell walk leaves
-                    // the box - and the coarse cell there is the walk's cell: every
-                    // plane with parameter <= t* crossed (cell_at).
-                    const int rr = cd - 1;
-                    double tn = __builtin_inf();
-                    bool domain = false;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const int dir = axis_dir(R, a);
-                        if (dir == 0) continue;
-                        int face = dir > 0 ? cc[a] + rr + 1 : cc[a] - rr;
-                        face = face < 0 ? 0 : (face > u.tc[a] ? u.tc[a] : face);
-                        const double tf = tau_plane(R, LC, a, face);
-                        const bool dom = dir > 0 ? face == u.tc[a] : face == 0;
-                        if (tf < tn) { tn = tf; domain = dom; }
-                        else if (tf == tn) domain = domain || dom;
-                    }
-                    if (tn > R.tx || domain) { alive = false; break; }
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) cc[a] = cell_at(R, LC, a, tn, 0, tchi[a]);
-                    tcur = tn;
-                    cvalid = false;
-                } else {
-                    // empty coarse cell: step over it at the coarse level
-                    if (!cvalid) {
-                        walk_init(R, LC, cc, wc);
-                        cvalid = true;
-                    }
-                    double tn = walk_exit(wc);
-                    if (tn > R.tx || !walk_step(R, LC, wc, cc, tn, zero3, tchi)) { alive = false; break; }
-                    tcur = tn;
-                }
-                continue;
-            }
-            ++cmasks;
-            if (!bvalid) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    int lo = 4 * cc[a], hi = 4 * cc[a] + 3;
-                    if (hi > tbhi[a]) hi = tbhi[a];
-                    cb[a] = cell_at(R, LB, a, tcur, lo, hi);
-                }
-                walk_init(R, LB, cb, wb);
-                bvalid = true;
-                tau = fresh ? cell_entry(R, LB, cb) : tcur;
-                fresh = false;
-            }
-            cvalid = false;
-            // One exit from the block loop, with its reason: a single exit mask
-            // for the compiler to keep instead of one per break.
-            //   1 the rest is the next lane's, 2 all slots filled, 3 step guard,
-            //   4 the ray left the volume, 5 the walk entered another coarse cell
-            int why = 0;
-            do {
-                if (tau >= t_hi) {
-                    why = 1;
-                } else {
-                    const bool emit = tau >= t_lo && ((cm >> local_bit(cb)) & 1ull);
-                    if (emit) {
-                        const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * u.nb[1] + cb[1]) * u.nb[0] + cb[0]);
-                        s_slot[nbuf][threadIdx.x] = bid;
-                        found++;
-                        if (++nbuf == TR_BUF && (L == 1u || big)) {
-                            if (L == 1u) {
-                                for (uint32_t k = 0; k < TR_BUF; ++k) {
-                                    slots[flushed + k] = s_slot[k][threadIdx.x];
-                                    if (per_ray) pray[flushed + k] = i;
-                                }
-                            } else {
-                                gptr<uint32_t> d = sbuf + ((size_t)flushed * SEG_BIG_LANES + bli);
-#pragma unroll 1
-                                for (uint32_t k = 0; k < TR_BUF; ++k, d += SEG_BIG_LANES) *d = s_slot[k][threadIdx.x];
-                            }
-                            flushed += TR_BUF;
-                            nbuf = 0;
+        // The walk's one exit is the loop condition (a single exit mask for the
+        // compiler): oexit 1 step guard, 2 the rest is the next lane's, 3 the
+        // ray left the volume; or every slot filled.
+        int oexit = alive ? 0 : 3;
+        while (oexit == 0 && found < nsr) {
+            if (++steps > max_steps) {   // every step advances an index
+                oexit = 1;
+            } else if (tcur >= t_hi && !fresh) {   // the rest is the next lane's
+                ++csteps;
+                oexit = 2;
+            } else {
+                ++csteps;
+                // The distance byte alone says whether the cell is empty (0 exactly for
+                // a cell with a candidate block): it is loaded first and tested first,
+                // so an empty cell's jump waits only for it.  The distances are 1 byte
+                // per coarse cell (2 MB at 2048x2048x1920, mostly L2 hits), the mask
+                // words 8 B (mostly misses).
+                const uint64_t cid = ((uint64_t)cc[2] * u.nc[1] + cc[1]) * u.nc[0] + cc[0];
+                const int cd = cdist[cid];
+                const uint64_t cm = cmask[cid];
+                if (cd != 0) {
+                    bvalid = false;
+                    fresh = false;   // the walk moves on to plane crossings
+                    if (cd >= 2) {
+                        // every coarse cell within cd-1 (chessboard) is empty: leave that box
+                        // in one jump.  t* = the first crossing of one of its faces (or of
+                        // the domain) - the parameter at which a cell-by-cell walk leaves
+                        // the box - and the coarse cell there is the walk's cell: every
+                        // plane with parameter <= t* crossed (cell_at).
+                        const int rr = cd - 1;
+                        double tn = __builtin_inf();
+                        bool domain = false;
+    #pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const int dir = axis_dir(R, a);
+                            if (dir == 0) continue;
+                            int face = dir > 0 ? cc[a] + rr + 1 : cc[a] - rr;
+                            face = face < 0 ? 0 : (face > u.tc[a] ? u.tc[a] : face);
+                            const double tf = tau_plane(R, LC, a, face);
+                            const bool dom = dir > 0 ? face == u.tc[a] : face == 0;
+                            if (tf < tn) { tn = tf; domain = dom; }
+                            else if (tf == tn) domain = domain || dom;
                         }
-                    }
-                    if (found == nsr) {
-                        why = 2;
-                    } else if (++steps > max_steps) {
-                        why = 3;
-                    } else {
-                        const double tn = walk_exit(wb);
-                        if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) {
-                            why = 4;
+                        if (tn > R.tx || domain) {
+                            oexit = 3;
                         } else {
+    #pragma unroll
+                            for (int a = 0; a < 3; ++a) cc[a] = cell_at(R, LC, a, tn, 0, tchi[a]);
                             tcur = tn;
-                            tau = tn;
-                            if ((cb[0] >> 2) != cc[0] || (cb[1] >> 2) != cc[1] || (cb[2] >> 2) != cc[2]) why = 5;
+                            cvalid = false;
+                        }
+                    } else {
+                        // empty coarse cell: step over it at the coarse level
+                        if (!cvalid) {
+                            walk_init(R, LC, cc, wc);
+                            cvalid = true;
+                        }
+                        double tn = walk_exit(wc);
+                        if (tn > R.tx || !walk_step(R, LC, wc, cc, tn, zero3, tchi)) oexit = 3;
+                        else tcur = tn;
+                    }
+                } else {
+                ++cmasks;
+                if (!bvalid) {
+    #pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        int lo = 4 * cc[a], hi = 4 * cc[a] + 3;
+                        if (hi > tbhi[a]) hi = tbhi[a];
+                        cb[a] = cell_at(R, LB, a, tcur, lo, hi);
+                    }
+                    walk_init(R, LB, cb, wb);
+                    bvalid = true;
+                    tau = fresh ? cell_entry(R, LB, cb) : tcur;
+                    fresh = false;
+                }
+                cvalid = false;
+                // One exit from the block loop, with its reason: a single exit mask
+                // for the compiler to keep instead of one per break.
+                //   1 the rest is the next lane's, 2 all slots filled, 3 step guard,
+                //   4 the ray left the volume, 5 the walk entered another coarse cell
+                int why = 0;
+                do {
+                    if (tau >= t_hi) {
+                        why = 1;
+                    } else {
+                        const bool emit = tau >= t_lo && ((cm >> local_bit(cb)) & 1ull);
+                        if (emit) {
+                            const uint32_t bid = (uint32_t)(((uint64_t)cb[2] * u.nb[1] + cb[1]) * u.nb[0] + cb[0]);
+                            s_slot[nbuf][threadIdx.x] = bid;
+                            found++;
+                            if (++nbuf == TR_BUF && (L == 1u || big)) {
+                                if (L == 1u) {
+                                    for (uint32_t k = 0; k < TR_BUF; ++k) {
+                                        slots[flushed + k] = s_slot[k][threadIdx.x];
+                                        if (per_ray) pray[flushed + k] = i;
+                                    }
+                                } else {
+                                    gptr<uint32_t> d = sbuf + ((size_t)flushed * SEG_BIG_LANES + bli);
+    #pragma unroll 1
+                                    for (uint32_t k = 0; k < TR_BUF; ++k, d += SEG_BIG_LANES) *d = s_slot[k][threadIdx.x];
+                                }
+                                flushed += TR_BUF;
+                                nbuf = 0;
+                            }
+                        }
+                        if (found == nsr) {
+                            why = 2;
+                        } else if (++steps > max_steps) {
+                            why = 3;
+                        } else {
+                            const double tn = walk_exit(wb);
+                            if (tn > R.tx || !walk_step(R, LB, wb, cb, tn, zero3, tbhi)) {
+                                why = 4;
+                            } else {
+                                tcur = tn;
+                                tau = tn;
+                                if ((cb[0] >> 2) != cc[0] || (cb[1] >> 2) != cc[1] || (cb[2] >> 2) != cc[2]) why = 5;
+                            }
                         }
                     }
-                }
-            } while (why == 0);
-            if (why == 1) break;
-            if (why == 3) { alive = false; guard_hit = true; break; }
-            if (why == 4) { alive = false; break; }
-            if (why == 5) {
+                } while (why == 0);
+                    oexit = why == 1 ? 2 : (why == 3 ? 1 : (why == 4 ? 3 : 0));
+                    if (why == 5) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
+                        for (int a = 0; a < 3; ++a) cc[a] = cb[a] >> 2;
+                    }
+                }
             }
         }
+        guard_hit = oexit == 1;
         if (guard_hit) atomicAdd(&ctl->guard, 1u);   // counted, so that tests can assert it never happens
         // The block of pair 0 (the first active ray's first candidate) takes
         // visible-list index 0, so it is always admitted and every pass makes
