@@ -151,6 +151,10 @@ struct spr_render {
     PassGrids grids{};
     bool started = false;       // a pass has run
     spr_batch *batch = nullptr;
+    // the request state as last read back, valid while no work that changes it
+    // has been enqueued since (a pass, a batch membership)
+    bool st_valid = false;
+    ReqState st_cache{};
     float last_ms = 0.f;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -385,6 +389,19 @@ spr_status read_ctl(spr_ctx *c, PassCtl *h) {
     HIPCHK(hipMemcpyAsync((char *)c->pinned + 256, c->ctl, sizeof(PassCtl), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     memcpy(h, (char *)c->pinned + 256, sizeof(PassCtl));
+    return SPR_OK;
+}
+
+// The render's state: the copy read at the end of its last run while no pass
+// was enqueued since, else read back (one copy and a stream synchronisation).
+static spr_status render_state(spr_render *r, ReqState *s) {
+    if (r->st_valid && !r->batch) {
+        *s = r->st_cache;
+        return SPR_OK;
+    }
+    CHK(read_state(r->ctx, r->d_st, s));
+    r->st_cache = *s;
+    r->st_valid = !r->batch;
     return SPR_OK;
 }
 
@@ -978,7 +995,7 @@ static spr_status fill_stats(spr_render *r, spr_pass_stats *o, float ms) {
     spr_ctx *c = r->ctx;
     ReqState s;
     PassCtl p;
-    CHK(read_state(c, r->d_st, &s));
+    CHK(render_state(r, &s));
     CHK(read_ctl(c, &p));
     memset(o, 0, sizeof(*o));
     o->pass = s.passes;
@@ -1001,6 +1018,7 @@ spr_status spr_render_pass(spr_render *r, spr_pass_stats *stats) {
     if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
     spr_ctx *c = r->ctx;
     HIPCHK(hipSetDevice(c->device));
+    r->st_valid = false;
     if (stats) HIPCHK(hipEventRecord(c->ev0, c->stream));
     if (c->prof) CHK(run_pass(c, r->table, r->grids));
     else CHK(graph_pass(c, r->table, r->grids, r->graph, r->exec, r->graph_gen));
@@ -1020,7 +1038,7 @@ spr_status spr_render_done(spr_render *r, int *done) {
     spr_ctx *c = r->ctx;
     HIPCHK(hipSetDevice(c->device));
     ReqState s;
-    CHK(read_state(c, r->d_st, &s));
+    CHK(render_state(r, &s));
     *done = s.n_act == 0;
     return SPR_OK;
 }
@@ -1030,8 +1048,16 @@ spr_status spr_render_run(spr_render *r, uint32_t max_passes, uint32_t *passes_r
     if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
     spr_ctx *c = r->ctx;
     HIPCHK(hipSetDevice(c->device));
-    ReqState s0;
-    CHK(read_state(c, r->d_st, &s0));
+    // A render that has not run a pass starts at pass 0 with its active rays
+    // unknown here: it is taken as not finished (a pass on a finished render
+    // does no work), which saves reading the state back first.
+    ReqState s0{};
+    if (r->started || r->st_valid) {
+        CHK(render_state(r, &s0));
+    } else {
+        s0.passes = 0;
+        s0.n_act = r->npix;
+    }
     const uint32_t start = s0.passes;
     // Keep two passes in flight: after enqueuing pass i+1, wait for pass i's
     // copy of N_act.  A pass on a finished render does no work, so the one
@@ -1058,9 +1084,9 @@ spr_status spr_render_run(spr_render *r, uint32_t max_passes, uint32_t *passes_r
         done = last_act == 0;
         ++waited;
     }
-    HIPCHK(hipStreamSynchronize(c->stream));
     ReqState s1;
-    CHK(read_state(c, r->d_st, &s1));
+    r->st_valid = false;
+    CHK(render_state(r, &s1));   // synchronises the stream; kept for get_info and done
     if (passes_run) *passes_run = s1.passes - start;
     return SPR_OK;
 }
@@ -1070,7 +1096,7 @@ spr_status spr_render_get_info(spr_render *r, spr_render_info *o) {
     spr_ctx *c = r->ctx;
     HIPCHK(hipSetDevice(c->device));
     ReqState s;
-    CHK(read_state(c, r->d_st, &s));
+    CHK(render_state(r, &s));
     memset(o, 0, sizeof(*o));
     o->w = r->w;
     o->h = r->h;
@@ -1192,7 +1218,10 @@ spr_status spr_batch_set(spr_batch *b, uint32_t n, spr_render *const *renders) {
     CHK(set_table_count(c, b->table, n));
     for (auto *r : b->renders) r->batch = nullptr;
     b->renders.assign(renders, renders + n);
-    for (auto *r : b->renders) r->batch = b;
+    for (auto *r : b->renders) {
+        r->batch = b;
+        r->st_valid = false;   // batch passes change its state
+    }
     b->state_fresh = false;
     return SPR_OK;
 }
