@@ -128,6 +128,8 @@ struct spr_ctx {
     double prof_ms[PROF_SLOTS] = {};
     uint64_t prof_n[PROF_SLOTS] = {};
     void *pinned = nullptr;     // small host staging area
+    uint32_t *nact_host = nullptr;   // fine-grained host word: active rays after a render's last pass
+    uint32_t *nact_dev = nullptr;    // its device address
     void *noalloc = nullptr;    // this device's copy of the allocation-free decode's staging
     int n_renders = 0;
 };
@@ -519,6 +521,13 @@ spr_status spr_ctx_create(const spr_config *cfg, spr_ctx **out) {
         spr_ctx_destroy(c);
         return fail(SPR_E_OOM, "pinned host allocation failed");
     }
+    // the pass end writes a render's active-ray count here, so the host polls
+    // it without a copy per pass (fine-grained: the write reaches host memory)
+    if (hipHostMalloc((void **)&c->nact_host, 256, hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->nact_dev, c->nact_host, 0) != hipSuccess) {
+        spr_ctx_destroy(c);
+        return fail(SPR_E_OOM, "pinned host allocation failed");
+    }
     bool evok = true;
 
     if (!evok || hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
@@ -567,6 +576,7 @@ spr_status spr_ctx_destroy(spr_ctx *c) {
     dfree(c, MEM_SCRATCH, c->ctl, 1);
     dfree(c, MEM_SCRATCH, c->d_vols, MAX_VOLUMES);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->nact_host) (void)hipHostFree(c->nact_host);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -934,6 +944,7 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     cv.add(&q.cmask64, r->cwords);
     cv.add(&q.cdist, 2 * r->cwords);
     carve_table(cv, 1, round64h(npix), npix, r->table);
+    r->table.host_nact = c->nact_dev;
     spr_status st = cv.alloc(c, MEM_RAYS, &r->buf, &r->buf_bytes);
     if (st == SPR_OK) st = ensure_work(c, npix);
     if (st != SPR_OK) {
@@ -1067,20 +1078,22 @@ spr_status spr_render_run(spr_render *r, uint32_t max_passes, uint32_t *passes_r
     const int DEPTH = 2;
     const uint32_t NEAR_END = r->npix / 256u > 256u ? r->npix / 256u : 256u;
     hipEvent_t ev[DEPTH] = {c->ev0, c->ev1};
-    volatile uint32_t *flag = (volatile uint32_t *)((char *)c->pinned + 3840);   // clear of the other staging areas
+    // the pass end of every pass of this render writes its active-ray count
+    // to this fine-grained host word; after pass i's event it holds the count
+    // after pass i or a later one (counts only fall)
+    volatile uint32_t *flag = (volatile uint32_t *)c->nact_host;
     uint32_t enq = 0, waited = 0, last_act = s0.n_act;
     bool done = s0.n_act == 0;
     while (!done) {
         const uint32_t depth = last_act <= NEAR_END ? 1u : (uint32_t)DEPTH;
         while (enq < max_passes && enq - waited < depth) {
             CHK(spr_render_pass(r, nullptr));
-            HIPCHK(hipMemcpyAsync((void *)(flag + (enq % DEPTH)), &r->d_st->n_act, 4, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipEventRecord(ev[enq % DEPTH], c->stream));
             ++enq;
         }
         if (waited == enq) break;   // max_passes reached
         HIPCHK(hipEventSynchronize(ev[waited % DEPTH]));
-        last_act = flag[waited % DEPTH];
+        last_act = flag[0];
         done = last_act == 0;
         ++waited;
     }

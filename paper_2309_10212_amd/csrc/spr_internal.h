@@ -222,6 +222,9 @@ struct Table {
     uint32_t *wave_off;         // exclusive prefix of the survivors
     uint32_t *wave_w;           // per wave of the A space: summed weights of its rays for the next pass
                                 // (per-ray counts; cleared by the compaction like the records)
+    uint32_t *host_nact;        // single-render tables: a fine-grained host word the pass end
+                                // writes request 0's active-ray count to (the host polls it);
+                                // null for batches
     uint32_t cap;               // request capacity
     uint32_t max_A;             // capacity of the A space (sum of padded npix)
     uint32_t max_P;             // capacity of the pair space (sum of npix)

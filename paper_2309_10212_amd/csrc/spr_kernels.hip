@@ -1886,6 +1886,8 @@ __global__ __launch_bounds__(PE_THREADS) void k_pass_end(PassCtl *ctl, Table T, 
         st->last_terminated = s_req[3][r];
         st->tot_pairs = tot + s_req[1][r];
         st->n_spec = ns;
+        // a single render's host polls its active-ray count here
+        if (r == 0 && T.host_nact) __hip_atomic_store(T.host_nact, na, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
