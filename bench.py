@@ -396,8 +396,10 @@ def run_rm(args):
     value = rays / el
     nb_vol = (RM_DIMS[0] // 4) * (RM_DIMS[1] // 4) * (RM_DIMS[2] // 4)
     nc_vol = ((RM_DIMS[0] // 4 + 3) // 4) * ((RM_DIMS[1] // 4 + 3) // 4) * ((RM_DIMS[2] // 4 + 3) // 4)
-    extra_counts = {"load_blocks": 0, "load_coarse": 0, "mask_coarse": nc_vol * steps,
-                    "mask_blocks": 64 * sum(i["iso_coarse_cells"] for i in infos),
+    # masks are built by the requests that found no kept set for their isovalue
+    built = [i for i in infos if i["masks_built"]]
+    extra_counts = {"load_blocks": 0, "load_coarse": 0, "mask_coarse": nc_vol * len(built),
+                    "mask_blocks": 64 * sum(i["iso_coarse_cells"] for i in built),
                     "setup_pixels": w * h * steps}
     dc.update(extra_counts)
     log(f"[bench] plain: {steps} requests, {value / 1e6:.1f} M rays/s, {el * 1e3 / steps:.3f} ms per request, "
@@ -627,9 +629,10 @@ def run_fourier(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     dc = _counter_delta(c0, ctx.counters())
+    built = [i for i in infos if i["masks_built"]]
     dc.update({"load_blocks": 0, "load_coarse": 0, "setup_pixels": args.w * args.h * args.steps,
-               "mask_blocks": 64 * sum(i["iso_coarse_cells"] for i in infos),
-               "mask_coarse": ((((n + 3) // 4) + 3) // 4) ** 3 * args.steps})
+               "mask_blocks": 64 * sum(i["iso_coarse_cells"] for i in built),
+               "mask_coarse": ((((n + 3) // 4) + 3) // 4) ** 3 * len(built)})
     ktimes, dcp, prof_ms = {}, dc, None
     if not args.no_profile:
         vol.free()

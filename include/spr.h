@@ -160,6 +160,9 @@ typedef struct {
                                  block that may hold the surface (the BCMC comparison, Sec. 5) decodes */
     uint64_t iso_coarse_cells; /* coarse cells whose range contains the isovalue (Sec. 3.1): the ones whose
                                  blocks' fine ranges the isovalue masks read */
+    uint32_t masks_built;     /* 1: this render built its isovalue masks and empty-space distances;
+                                 0: it reads a set that its volume kept from an earlier render with the
+                                 same isovalue (both counts above are that set's) */
 } spr_render_info;
 
 /* Accumulated device time of one kernel of the pass (profiling mode). */
@@ -172,9 +175,11 @@ typedef struct {
 /* Device memory by what it holds (Sec. 5.3 reports total and cache memory).
  * Kinds: SPR_MEM_COMPRESSED (compressed streams), SPR_MEM_GRIDS (macrocell
  * grids and per-block state: fine and coarse ranges, block-to-slot map, pair
- * counters, visible index, active stamps), SPR_MEM_RAYS (per-render buffers:
- * ray state, active lists, pair slots, hit records, image, hit buffer,
- * isovalue masks and empty-space distances), SPR_MEM_CACHE (the decoded-block
+ * counters, visible index, active stamps, the isovalue mask sets a volume
+ * keeps), SPR_MEM_RAYS (per-render buffers: ray state, active lists, pair
+ * slots, hit records, image, hit buffer, and the isovalue masks and
+ * empty-space distances of a render that could not use a kept set),
+ * SPR_MEM_CACHE (the decoded-block
  * cache: 256-byte slots, owners, LRU stamps, free stack), SPR_MEM_SCRATCH
  * (pass workspace, control block, batch tables, debug staging). */
 #define SPR_MEM_COMPRESSED 0
@@ -279,7 +284,15 @@ spr_status spr_debug_fp64_ops(spr_ctx *ctx, const double *x, const double *y, si
 /* Start a render: computes every pixel's ray and its entry into the volume
  * (Sec. 3.2); rays that miss are terminated, the image is cleared to 0 and
  * the hit buffer to "no hit".  w*h must be < 2^24; the camera must not look
- * along its up vector.  isovalue is compared in float32. */
+ * along its up vector.  isovalue is compared in float32.
+ * The render also needs the volume's isovalue masks and empty-space
+ * distances (one u64 and one byte per coarse cell, derived from the grids of
+ * Sec. 3.1 and the isovalue).  A volume keeps up to 4 such sets, one per
+ * isovalue (compared bitwise): a render whose isovalue has a kept set reads
+ * it; otherwise it builds one into the least recently used set that no live
+ * render reads, or into buffers of its own when every set is in use.
+ * spr_volume_build_grids drops the kept sets' keys; spr_volume_free frees
+ * them. */
 spr_status spr_render_begin(spr_volume *vol, const spr_camera *cam, float isovalue, uint32_t w, uint32_t h,
                             spr_render **out);
 /* Speculation cap of this render (Sec. 4 caps N_spec at 64); 1 disables

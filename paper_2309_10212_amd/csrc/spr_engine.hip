@@ -134,12 +134,32 @@ struct spr_ctx {
     int n_renders = 0;
 };
 
+// Isovalue masks and empty-space distances depend only on the volume's
+// ranges and the isovalue, so a volume keeps the sets of its last few
+// isovalues: a render whose isovalue matches a kept set (bitwise) reads that
+// set instead of building its own.  A set that a live render reads is never
+// rebuilt; when every set is in use, a render builds private masks.
+struct MaskSet {
+    uint32_t iso_bits = 0;
+    bool keyed = false;          // holds (or, in stream order, will hold) the masks of iso_bits
+    int users = 0;               // live renders reading it
+    uint64_t last_use = 0;       // replacement order among the sets nobody reads
+    void *buf = nullptr;         // counts, masks and distances, carved from one allocation
+    size_t bytes = 0;
+    unsigned long long *mstat = nullptr;
+    uint64_t *cmask64 = nullptr;
+    uint8_t *cdist = nullptr;
+};
+constexpr int MASK_SETS = 4;
+
 struct spr_volume {
     spr_ctx *ctx = nullptr;
     uint32_t idx = 0;
     spr_volume_desc desc{};
     size_t stream_bytes = 0;
     int n_renders = 0;
+    MaskSet msets[MASK_SETS];
+    uint64_t mask_clock = 0;
 };
 
 struct spr_render {
@@ -162,6 +182,8 @@ struct spr_render {
     hipGraphExec_t exec = nullptr;
     uint64_t graph_gen = ~0ull;
     uint64_t cwords = 0;   // isovalue mask size (one u64 per coarse cell)
+    int mset = -1;         // the volume's mask set this render reads (-1: its own masks)
+    bool masks_built = true;   // this render built its masks (else a kept set served them)
     void *buf = nullptr;   // every device buffer of the render, carved from one allocation
     size_t buf_bytes = 0;
 };
@@ -795,6 +817,10 @@ spr_status spr_volume_free(spr_volume *v) {
     HIPCHK(hipMemcpyAsync(c->d_vols + v->idx, &V, sizeof(VolDev), hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     free_volume_buffers(c, V, v->stream_bytes);
+    for (MaskSet &m : v->msets) {
+        dev_free(c, MEM_GRIDS, m.buf, m.bytes);
+        m = MaskSet{};
+    }
     c->vol_handles[v->idx] = nullptr;
     delete v;
     return SPR_OK;
@@ -807,6 +833,9 @@ spr_status spr_volume_build_grids(spr_volume *v) {
     hipEvent_t *ev = nullptr;
     if (c->prof) CHK(prof_begin(c, 3, LOAD_SLOTS, &ev));
     HIPCHK(launch_load_grids(c->stream, c->h_vols[v->idx], ev));
+    // kept masks were built from the ranges just rewritten: new renders build
+    // theirs again (sets in use keep serving their renders)
+    for (MaskSet &m : v->msets) m.keyed = false;
     return SPR_OK;
 }
 
@@ -896,6 +925,55 @@ static void free_render_buffers(spr_ctx *c, spr_render *r) {
     r->buf_bytes = 0;
 }
 
+// The volume's mask set for iso: a kept one (*build = false), or the least
+// recently used set that no live render reads, keyed to iso (*build = true,
+// allocated on first use); *idx = -1 when every set is in use.
+static spr_status mask_set_acquire(spr_ctx *c, spr_volume *v, float iso, uint64_t cwords, int *idx, bool *build) {
+    uint32_t bits;
+    memcpy(&bits, &iso, sizeof bits);
+    *idx = -1;
+    *build = true;
+    int pick = -1;
+    for (int i = 0; i < MASK_SETS && pick < 0; ++i)
+        if (v->msets[i].keyed && v->msets[i].iso_bits == bits) pick = i;
+    if (pick >= 0) {
+        *build = false;
+    } else {
+        for (int i = 0; i < MASK_SETS; ++i) {
+            const MaskSet &m = v->msets[i];
+            if (m.users) continue;
+            if (pick < 0) { pick = i; continue; }
+            const MaskSet &b = v->msets[pick];
+            if ((b.keyed && !m.keyed) || (b.keyed == m.keyed && m.last_use < b.last_use)) pick = i;
+        }
+        if (pick < 0) return SPR_OK;
+        MaskSet &m = v->msets[pick];
+        if (!m.buf) {
+            Carve cv;
+            cv.add(&m.mstat, 2);
+            cv.add(&m.cmask64, cwords);
+            cv.add(&m.cdist, 2 * cwords);
+            CHK(cv.alloc(c, MEM_GRIDS, &m.buf, &m.bytes));
+        }
+        m.iso_bits = bits;
+        m.keyed = true;
+    }
+    MaskSet &m = v->msets[pick];
+    m.users++;
+    m.last_use = ++v->mask_clock;
+    *idx = pick;
+    return SPR_OK;
+}
+
+// A render stops reading its mask set; unkey: the set was to be built by a
+// render whose set-up failed, so it holds no masks.
+static void mask_set_release(spr_volume *v, int idx, bool unkey) {
+    if (idx < 0) return;
+    MaskSet &m = v->msets[idx];
+    m.users--;
+    if (unkey) m.keyed = false;
+}
+
 spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uint32_t w, uint32_t h,
                             spr_render **out) {
     if (!v || !cam || !out) return fail(SPR_E_INVALID, "null argument");
@@ -924,6 +1002,20 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
         const VolDev &V = c->h_vols[v->idx];
         r->cwords = (uint64_t)V.nc[0] * V.nc[1] * V.nc[2];
     }
+    {
+        spr_status ms = mask_set_acquire(c, v, iso, r->cwords, &r->mset, &r->masks_built);
+        if (ms != SPR_OK) {
+            delete r;
+            return ms;
+        }
+    }
+    if (r->mset >= 0) {
+        const MaskSet &m = v->msets[r->mset];
+        q.cmask64 = m.cmask64;
+        q.cdist = m.cdist;
+        q.mstat = m.mstat;
+        q.mstat_load = r->masks_built ? 0u : 1u;
+    }
     Carve cv;
     cv.add(&q.ray_state, npix);
     cv.add(&q.act[0], npix);
@@ -941,14 +1033,17 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     cv.add(&q.hits, npix);
     cv.add(&r->d_st, 1);
     cv.add(&r->d_req, 1);
-    cv.add(&q.cmask64, r->cwords);
-    cv.add(&q.cdist, 2 * r->cwords);
+    if (r->mset < 0) {
+        cv.add(&q.cmask64, r->cwords);
+        cv.add(&q.cdist, 2 * r->cwords);
+    }
     carve_table(cv, 1, round64h(npix), npix, r->table);
     r->table.host_nact = c->nact_dev;
     spr_status st = cv.alloc(c, MEM_RAYS, &r->buf, &r->buf_bytes);
     if (st == SPR_OK) st = ensure_work(c, npix);
     if (st != SPR_OK) {
         free_render_buffers(c, r);
+        mask_set_release(v, r->mset, r->masks_built);
         delete r;
         return st;
     }
@@ -962,10 +1057,13 @@ spr_status spr_render_begin(spr_volume *v, const spr_camera *cam, float iso, uin
     // (kernel arguments: no host synchronisation)
     hipError_t e = launch_put_req(c->stream, r->d_req, q, r->d_st, &s0, r->table.hdr, 1u);
     hipEvent_t *pev = nullptr;
-    if (e == hipSuccess && c->prof && prof_begin(c, 5, INIT_SLOTS, &pev) != SPR_OK) e = hipErrorUnknown;
-    if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols, r->cwords, pev);
+    const bool build = r->masks_built;
+    if (e == hipSuccess && c->prof && prof_begin(c, build ? 5 : 4, build ? INIT_SLOTS : INIT_SLOTS + 1, &pev) != SPR_OK)
+        e = hipErrorUnknown;
+    if (e == hipSuccess) e = launch_init_rays(c->stream, c->ctl, r->table, c->d_vols, r->cwords, build, pev);
     if (e != hipSuccess) {
         free_render_buffers(c, r);
+        mask_set_release(v, r->mset, build);
         delete r;
         return fail(SPR_E_HIP, "render set-up failed: %s", hipGetErrorString(e));
     }
@@ -1125,6 +1223,7 @@ spr_status spr_render_get_info(spr_render *r, spr_render_info *o) {
     o->pairs = s.tot_pairs;
     o->bcmc_blocks = s.bcmc;
     o->iso_coarse_cells = s.ccells;
+    o->masks_built = r->masks_built ? 1u : 0u;
     return SPR_OK;
 }
 
@@ -1164,6 +1263,7 @@ spr_status spr_render_free(spr_render *r) {
     if (r->exec) (void)hipGraphExecDestroy(r->exec);
     if (r->graph) (void)hipGraphDestroy(r->graph);
     free_render_buffers(c, r);
+    mask_set_release(r->vol, r->mset, false);
     r->vol->n_renders--;
     c->n_renders--;
     delete r;

@@ -142,7 +142,7 @@ struct ReqDev {
     uint32_t vol;               // index in the context's volume table
     uint32_t spec_cap;
     uint32_t policy;            // SPEC_UNIFORM or SPEC_PER_RAY
-    uint32_t pad;
+    uint32_t mstat_load;        // with mstat: 1 when the masks were built by an earlier render
     uint32_t *ray_state;        // per pixel: last served block, RAY_NOT_STARTED, RAY_DONE
     uint32_t *act[2];           // compacted active pixel lists
     uint32_t *pair_blk;         // per pair slot (R_BID of Sec. 3.3/4.1)
@@ -163,6 +163,8 @@ struct ReqDev {
     uint8_t *cdist;             // per coarse cell: chessboard distance (in coarse cells, capped at
                                 // CD_MAX) to the nearest coarse cell with a nonzero mask; a second
                                 // nc bytes after it are scratch for the separable passes
+    unsigned long long *mstat;  // counts of a mask set the volume keeps (bcmc, ccells), or null
+                                // when the masks are the render's own
 };
 
 constexpr int CD_MAX = 15;

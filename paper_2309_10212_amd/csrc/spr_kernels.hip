@@ -525,6 +525,21 @@ __device__ __forceinline__ uint32_t tile_pixel(uint32_t i, uint32_t w, uint32_t 
 
 __global__ void k_init_rays(PassCtl *ctl, Table T, const VolDev *vols) {
     uint32_t A = ctl->A;
+    // a mask set kept by the volume carries the counts of the render that
+    // built it; renders that reuse the set take them from there
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (uint32_t r = 0; r < ctl->nreq; ++r) {
+            const ReqDev &q = T.reqs[r];
+            unsigned long long *ms = q.mstat;
+            if (ms && q.mstat_load) {
+                q.st->bcmc = ms[0];
+                q.st->ccells = ms[1];
+            } else if (ms) {
+                ms[0] = q.st->bcmc;
+                ms[1] = q.st->ccells;
+            }
+        }
+    }
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < A; p += gridDim.x * blockDim.x) {
         // all lanes of a wave share a request (the A space is 64-aligned per request)
         uint32_t r = __builtin_amdgcn_readfirstlane(find_req(T.act_base, ctl->nreq, p));
@@ -2024,17 +2039,19 @@ hipError_t launch_release_volume(hipStream_t s, PassCtl *ctl, const Cache &C, ui
 }
 
 hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words,
-                            hipEvent_t *ev) {
+                            bool build_masks, hipEvent_t *ev) {
     int k = 0;
     auto mark = [&]() {
         if (ev) (void)hipEventRecord(ev[k], s);
         ++k;
     };
-    mark();   // masks, then the empty-space distances (timed together)
-    hipLaunchKernelGGL(k_iso_masks, dim3(grid_for(mask_words, 256, 4096)), dim3(256), 0, s, T, vols);
-    hipLaunchKernelGGL(k_cdist_pass<0>, dim3(grid_for(mask_words, CD_TA * CD_TL, 4096)), dim3(256), 0, s, T, vols);
-    hipLaunchKernelGGL(k_cdist_pass<1>, dim3(grid_for(mask_words, CD_TA * CD_TL, 4096)), dim3(256), 0, s, T, vols);
-    hipLaunchKernelGGL(k_cdist_pass<2>, dim3(grid_for(mask_words, CD_TA * CD_TL, 4096)), dim3(256), 0, s, T, vols);
+    if (build_masks) {
+        mark();   // masks, then the empty-space distances (timed together)
+        hipLaunchKernelGGL(k_iso_masks, dim3(grid_for(mask_words, 256, 4096)), dim3(256), 0, s, T, vols);
+        hipLaunchKernelGGL(k_cdist_pass<0>, dim3(grid_for(mask_words, CD_TA * CD_TL, 4096)), dim3(256), 0, s, T, vols);
+        hipLaunchKernelGGL(k_cdist_pass<1>, dim3(grid_for(mask_words, CD_TA * CD_TL, 4096)), dim3(256), 0, s, T, vols);
+        hipLaunchKernelGGL(k_cdist_pass<2>, dim3(grid_for(mask_words, CD_TA * CD_TL, 4096)), dim3(256), 0, s, T, vols);
+    }
     mark(); hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(64), 0, s, ctl, T, 1);
     mark(); hipLaunchKernelGGL(k_init_rays, dim3(grid_for(T.max_A, 256, 16384)), dim3(256), 0, s, ctl, T, vols);
     mark(); hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(1024), 0, s, ctl, T, 1);

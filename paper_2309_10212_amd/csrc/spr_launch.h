@@ -36,11 +36,12 @@ hipError_t launch_fill_u32(hipStream_t s, uint32_t *p, uint64_t n, uint32_t v);
 hipError_t launch_fill_u64(hipStream_t s, uint64_t *p, uint64_t n, uint64_t v);
 hipError_t launch_iota_u32(hipStream_t s, uint32_t *p, uint64_t n);
 hipError_t launch_release_volume(hipStream_t s, PassCtl *ctl, const Cache &C, uint32_t vol);
-// Isovalue masks of the table's first request, then the initial-ray pass
-// (masks, pass set-up, initial rays, count, compaction); ev as for the load
-// path, with ev[5] after the last kernel.
+// Isovalue masks of the table's first request (when build_masks), then the
+// initial-ray pass (pass set-up, initial rays, count, compaction); ev as for
+// the load path, one event before each timed group and one after the last
+// (6 events with the masks, 5 without).
 hipError_t launch_init_rays(hipStream_t s, PassCtl *ctl, const Table &T, const VolDev *vols, uint64_t mask_words,
-                            hipEvent_t *ev = nullptr);
+                            bool build_masks, hipEvent_t *ev = nullptr);
 constexpr int PASS_KERNELS = 12;
 extern const char *const PASS_KERNEL_NAMES[PASS_KERNELS];
 // Profiling slots: the pass kernels, then the load-path and set-up kernels
@@ -48,7 +49,7 @@ extern const char *const PASS_KERNEL_NAMES[PASS_KERNELS];
 constexpr int PROF_SLOTS = PASS_KERNELS + 5;
 extern const char *const PROF_NAMES[PROF_SLOTS];
 constexpr int LOAD_SLOTS[3] = {PASS_KERNELS, PASS_KERNELS + 1, PASS_KERNELS + 2};   // block ranges, fine grid, coarse grid
-// masks, pass begin, initial rays, pass end, compact
+// masks, pass begin, initial rays, pass end, compact (INIT_SLOTS + 1: without the masks)
 constexpr int INIT_SLOTS[5] = {PASS_KERNELS + 3, 0, PASS_KERNELS + 4, PASS_KERNELS - 2, PASS_KERNELS - 1};
 // ev == nullptr: plain launches; else ev[i] is recorded before kernel i and
 // ev[PASS_KERNELS] after the last one.

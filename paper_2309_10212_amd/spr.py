@@ -82,7 +82,8 @@ class Counters(ctypes.Structure):
 class RenderInfo(ctypes.Structure):
     _fields_ = [("w", ctypes.c_uint32), ("h", ctypes.c_uint32), ("rays_entered", ctypes.c_uint32),
                 ("n_active", ctypes.c_uint32), ("n_spec", ctypes.c_uint32), ("passes", ctypes.c_uint32),
-                ("pairs", ctypes.c_uint64), ("bcmc_blocks", ctypes.c_uint64), ("iso_coarse_cells", ctypes.c_uint64)]
+                ("pairs", ctypes.c_uint64), ("bcmc_blocks", ctypes.c_uint64), ("iso_coarse_cells", ctypes.c_uint64),
+                ("masks_built", ctypes.c_uint32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

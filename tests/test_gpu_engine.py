@@ -150,6 +150,11 @@ def test_failing_allocator_gives_oom_and_leaks_nothing(fail_after):
         spr.Render(vol, cam, 0.5, 64, 64)
     assert e.value.status == -2
     ca.fail_after = None
+    # the failed set-up left no masks for its isovalue: the next render builds them
+    r = spr.Render(vol, cam, 0.5, 64, 64)
+    assert r.info()["masks_built"] == 1
+    r.run()
+    r.free()
     vol.free()
     ctx.close()
     assert ca.allocs == ca.frees and not ca.live

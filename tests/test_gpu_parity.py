@@ -329,6 +329,54 @@ def test_cache_too_small_for_one_block_is_rejected():
     assert e.value.status == -5
 
 
+def test_kept_isovalue_mask_sets(ctx):
+    """A volume keeps the isovalue masks of up to four isovalues: a render at
+    a kept isovalue reads them and their counts, one at a new isovalue takes
+    the least recently used set that no live render reads, and while every
+    set is read a render builds its own.  Every image equals the oracle's and
+    the counts equal the oracle's, whichever path served the masks."""
+    from paper_2309_10212_amd import spr
+    s, dec, cam = _tiny()
+    n, w, h = 64, 96, 80
+    vol = ctx.load_volume(s, (n, n, n), 8)
+    _, fine, coarse = oracle.grids(dec)
+    refs = {}
+
+    def begin(iso, built):
+        r = spr.Render(vol, cam, iso, w, h, spec_cap=16)
+        info = r.info()
+        assert info["masks_built"] == built, (iso, built, info)
+        assert info["bcmc_blocks"] == oracle.blocks_containing(fine, iso), iso
+        assert info["iso_coarse_cells"] == oracle.blocks_containing(coarse, iso), iso
+        return r
+
+    def finish(r, iso, label):
+        r.run()
+        if iso not in refs:
+            refs[iso] = oracle.render(dec, cam, iso, w, h)
+        _cmp_hits(r.hits(), r.image(), refs[iso], label)
+        r.free()
+
+    # one render at a time: (isovalue, expected masks_built)
+    seq = [(0.5, 1), (0.5, 0), (0.3, 1), (0.7, 1), (0.2, 1), (0.5, 0),
+           (0.6, 1),            # replaces 0.3, the least recently used set
+           (0.3, 1), (0.2, 0), (0.5, 0), (0.6, 0)]   # 0.3 replaces 0.7
+    for k, (iso, built) in enumerate(seq):
+        finish(begin(iso, built), iso, f"sequential {k} iso {iso}")
+    # kept now: 0.5, 0.6, 0.3, 0.2; while renders read all four, new
+    # isovalues build private masks and kept ones are still shared
+    live = [(iso, begin(iso, 0)) for iso in (0.5, 0.6, 0.3, 0.2)]
+    live += [(0.4, begin(0.4, 1)), (0.7, begin(0.7, 1)), (0.5, begin(0.5, 0))]
+    for k, (iso, r) in enumerate(live):
+        finish(r, iso, f"live {k} iso {iso}")
+    finish(begin(0.4, 1), 0.4, "after the live renders")
+    # rebuilding the grids drops every kept set
+    vol.build_grids()
+    finish(begin(0.5, 1), 0.5, "after a grid rebuild")
+    finish(begin(0.5, 0), 0.5, "kept again")
+    vol.free()
+
+
 def test_two_runs_bitwise_identical(ctx):
     from paper_2309_10212_amd import spr
     s, dec, cam = _tiny()
