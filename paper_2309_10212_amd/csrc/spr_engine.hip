@@ -1078,6 +1078,7 @@ spr_status spr_render_set_spec_cap(spr_render *r, uint32_t cap) {
     if (cap < 1 || cap > 4096) return fail(SPR_E_INVALID, "spec cap must be in 1..4096");
     if (r->started) return fail(SPR_E_STATE, "speculation cap can only change before the first pass");
     if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
+    if (cap == r->hreq.spec_cap) return SPR_OK;
     spr_ctx *c = r->ctx;
     HIPCHK(hipSetDevice(c->device));
     // the first pass takes its count from the cap in the description
@@ -1093,6 +1094,7 @@ spr_status spr_render_set_spec_policy(spr_render *r, uint32_t policy) {
         return fail(SPR_E_INVALID, "unknown speculation policy %u", policy);
     if (r->started) return fail(SPR_E_STATE, "the speculation policy can only change before the first pass");
     if (r->batch) return fail(SPR_E_STATE, "render belongs to a live batch");
+    if (policy == r->hreq.policy) return SPR_OK;
     spr_ctx *c = r->ctx;
     HIPCHK(hipSetDevice(c->device));
     r->hreq.policy = policy;
