@@ -332,7 +332,7 @@ PassGrids grids_for(const spr_ctx *c, uint64_t max_A, uint64_t max_P) {
     pg.slots = g(c->cache.n_slots, 256, 2048);
     pg.assign = 256;
     pg.scatter = g(max_P, 256, 2048);
-    pg.decode = g(8 * max_P, 64, 1024);
+    pg.decode = g(8 * max_P, 64, 4096);
     pg.max_P = max_P;
     pg.rt_tile = c->rt_tile;
     pg.rt_lb = c->rt_lb;

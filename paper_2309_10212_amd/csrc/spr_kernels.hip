@@ -1288,20 +1288,28 @@ __global__ __launch_bounds__(64) void k_decode(PassCtl *ctl, const VolDev *vols,
     fill_dep4(L, threadIdx.x);
     __syncthreads();
     const uint32_t m = ctl->assigned;
-    for (uint32_t i = blockIdx.x * 64 + threadIdx.x; i < m; i += gridDim.x * 64) {
-        uint64_t e = W.miss_list[i];
-        const VolDev &V = vols[(uint32_t)(e >> 32)];
-        const uint32_t *rec = V.stream + (uint64_t)(uint32_t)e * (uint64_t)V.rec_words;
-        decode_to<32>(rec, V.rate, L, threadIdx.x, C.slots + (size_t)W.miss_slot[i] * 64);
+    // The first nd workgroups decode the misses (one block per lane), the
+    // others list the neighbourhoods, so that a lane's decode and its share
+    // of the lists do not add up on one critical path (at most half of the
+    // grid, rounded up, decodes; a longer miss list takes several blocks per
+    // lane; a one-workgroup grid does both).
+    const uint32_t half = (gridDim.x + 1u) / 2u;
+    const uint32_t nd = (m + 63u) / 64u < half ? (m + 63u) / 64u : half;
+    if (blockIdx.x < nd) {
+        for (uint32_t i = blockIdx.x * 64 + threadIdx.x; i < m; i += nd * 64) {
+            uint64_t e = W.miss_list[i];
+            const VolDev &V = vols[(uint32_t)(e >> 32)];
+            const uint32_t *rec = V.stream + (uint64_t)(uint32_t)e * (uint64_t)V.rec_words;
+            decode_to<32>(rec, V.rate, L, threadIdx.x, C.slots + (size_t)W.miss_slot[i] * 64);
+        }
     }
     // Per admitted visible block, the slots of its 2x2x2 neighbourhood (every
     // neighbour is active, so it holds a slot by now): the raytrace reads them
-    // with the visible-list entry instead of eight map lookups after it.  The
-    // entries go to the workgroups from the end of the grid, which have no
-    // misses to decode unless the miss list is long.
+    // with the visible-list entry instead of eight map lookups after it.
     const uint32_t vadm = admitted_blocks(ctl);
-    const uint32_t wr = gridDim.x - 1u - blockIdx.x;
-    for (uint32_t v = wr * 64 + threadIdx.x; v < vadm; v += gridDim.x * 64) {
+    const uint32_t l0 = nd < gridDim.x ? nd : 0u;   // the list workgroups: l0 .. gridDim - 1
+    const uint32_t nl = gridDim.x - l0;
+    for (uint32_t v = (blockIdx.x - l0) * 64 + threadIdx.x; blockIdx.x >= l0 && v < vadm; v += nl * 64) {
         const uint64_t e = W.vis_list[v];
         const VolState V = vol_state(vols[(uint32_t)(e >> 32)]);
         const uint32_t b = (uint32_t)e;
