@@ -377,6 +377,37 @@ def test_kept_isovalue_mask_sets(ctx):
     vol.free()
 
 
+@pytest.mark.parametrize("w,h", [(8, 8), (6, 5)])
+def test_small_image_many_misses(ctx, w, h):
+    """A small image on a freshly loaded 64^3 Fourier field: the first pass
+    misses more blocks (324 and 136) than half of the decode grid's lanes
+    (256 and 128 for these images), so the decoding workgroups take several
+    blocks per lane while the others list the neighbourhoods.  Every pixel
+    and per-pass counter against the oracle."""
+    from paper_2309_10212_amd import spr
+    n = 64
+    f = volgen.fourier(n, n, n, seed=5, nmode=64, kmax=16, period=float(n))
+    iso = float(np.percentile(f, 50))
+    s = volgen.encode(f, 8)
+    dec = oracle.decode_volume(s, (n, n, n), 8)
+    cam = volgen.orbit_camera(n, n, n, seed=1)
+    vol = ctx.load_volume(s, (n, n, n), 8)
+    r = spr.Render(vol, cam, iso, w, h, spec_cap=64)
+    got = []
+    while not r.done():
+        got.append(r.pass_(stats=True))
+        assert len(got) < 50
+    sched = oracle.schedule(dec, cam, iso, w, h, 64)
+    assert len(got) == len(sched)
+    assert got[0]["blocks_decoded"] == sched[0]["active_blocks"] > 64 * (((8 * w * h + 63) // 64 + 1) // 2)
+    for p, (g, o) in enumerate(zip(got, sched)):
+        for k in ("n_active", "n_spec", "pairs", "visible", "active_blocks", "terminated"):
+            assert g[k] == o[k], (p, k, g, o)
+    _cmp_hits(r.hits(), r.image(), oracle.render(dec, cam, iso, w, h), f"fourier {w}x{h}")
+    r.free()
+    vol.free()
+
+
 def test_two_runs_bitwise_identical(ctx):
     from paper_2309_10212_amd import spr
     s, dec, cam = _tiny()
